@@ -1,0 +1,190 @@
+/*
+ * libsfrde -- one ETDRK4 step of a space-fractional reaction-diffusion system
+ * on an AMD MI355X (gfx950), behind a plain C ABI.
+ *
+ * The problem (Section 1, eq. 1):  u_t = -kappa (-Delta)^(alpha/2) u + f(u, t)
+ * on a box in 2D or 3D with periodic, homogeneous Dirichlet or homogeneous
+ * Neumann boundary conditions, for S coupled species.
+ *
+ * Space (Section 3): the compact fourth-order Laplacian A^-1 B raised to
+ * alpha/2 by the matrix transfer technique (eq. MTT). It is diagonal in the
+ * basis of the boundary condition's transform (discrete Hartley for periodic,
+ * DST-I for Dirichlet, weighted DCT-I for Neumann), with eigenvalues
+ * lambda_k = 4 s^2 / (h^2 (1 - s^2/3)) per axis, summed over the axes
+ * (Sections 3.1-3.3, E16-E18, E22).
+ *
+ * Time (Section 4, eq. ETDRK4P13 and Alg. 1): four stages per step, each a
+ * forward transform of the reaction, a diagonal multiply-and-combine with six
+ * coefficient arrays of L = kappa dt Lambda^(alpha/2), an inverse transform
+ * and a pointwise reaction. Two coefficient schemes: the paper's Pade-based
+ * ETDRK4-P13 (default) and the exact-exponential ETDRK4 of Cox and Matthews.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Fields are device arrays [S][nz][ny][nx] (2D: [S][ny][nx]) of the plan's
+ *   dtype, x contiguous. Sizes are *unknowns* per axis: N = n (periodic),
+ *   n + 1 (Dirichlet), n - 1 (Neumann) intervals with spacing h per axis.
+ * - n[0] is the x (fastest) extent, n[1] y, n[2] z; h[] in the same order.
+ * - The caller owns every buffer passed in (state, checkpoints, gradients)
+ *   and the stream; the library never frees caller memory. The plan owns its
+ *   tables and workspace; sfrde_destroy frees them.
+ * - All work is enqueued on the plan's stream. sfrde_integrate synchronizes
+ *   once at its end (to report non-finite values); sfrde_backward
+ *   synchronizes at its end (host scalar outputs).
+ * - Return codes are SFRDE_OK (0) or a negative sfrde_status; the message
+ *   for the last failure on the calling thread is sfrde_last_error().
+ * - A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef SFRDE_H
+#define SFRDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFRDE_MAX_SPECIES 4
+#define SFRDE_MAX_PARAMS 16
+#define SFRDE_CKPT_HEADER_BYTES 256
+
+typedef struct sfrde_plan_s* sfrde_plan_t;
+
+enum sfrde_status {
+  SFRDE_OK = 0,
+  SFRDE_EINVAL = -1,       /* bad argument; detected before any device call */
+  SFRDE_ENOMEM = -2,       /* device or host allocation failed */
+  SFRDE_EDEVICE = -3,      /* a HIP runtime call failed */
+  SFRDE_ENONFINITE = -4,   /* a stage value or reaction became NaN/Inf */
+  SFRDE_EUNSUPPORTED = -5, /* valid request this build does not support */
+  SFRDE_ESTATE = -6        /* checkpoint incompatible with the request */
+};
+
+enum sfrde_bc { SFRDE_BC_PERIODIC = 0, SFRDE_BC_DIRICHLET = 1, SFRDE_BC_NEUMANN = 2 };
+enum sfrde_dtype { SFRDE_F32 = 0, SFRDE_F64 = 1 };
+enum sfrde_scheme { SFRDE_SCHEME_P13 = 0, SFRDE_SCHEME_EXP = 1 };
+
+/* Reaction terms (Section 5.2) and their parameter vectors p[]:
+ *   LINEAR            p = (g_0..g_{S-1})         f_s = g_s u_s   (any S <= 4)
+ *   FHN               p = (mu, eps, beta, gamma, delta)
+ *                     f_u = u(1-u)(u-mu) - v,  f_v = eps(beta u - gamma v - delta)
+ *   GRAY_SCOTT        p = (F, K)
+ *                     f_u = -u v^2 + F(1-u),   f_v = u v^2 - (F+K) v
+ *   SCHNAKENBERG      p = (gamma, a, b)
+ *                     f_u = gamma(a - u + u^2 v),  f_v = gamma(b - u^2 v)
+ *   GIERER_MEINHARDT  p = (rho, mu_u, sigma_u, sigma_v, mu_v)
+ *                     f_u = rho - mu_u u + sigma_u u^2/v,  f_v = sigma_v u^2 - mu_v v
+ * All but LINEAR need S = 2. */
+enum sfrde_reaction {
+  SFRDE_RXN_LINEAR = 0,
+  SFRDE_RXN_FHN = 1,
+  SFRDE_RXN_GRAY_SCOTT = 2,
+  SFRDE_RXN_SCHNAKENBERG = 3,
+  SFRDE_RXN_GIERER_MEINHARDT = 4
+};
+
+/* Create a plan (Sections 3-4; Alg. 1 precompute).
+ *   out       receives the plan handle (host pointer, required)
+ *   ndim      2 or 3 (1 returns SFRDE_EUNSUPPORTED)
+ *   n[ndim]   unknowns per axis, x first; each >= 2, each <= 1024
+ *   bc        enum sfrde_bc, the same on every axis
+ *   h[ndim]   mesh width per axis (> 0)
+ *   nspecies  S, 1..4
+ *   alpha[S]  fractional order per species, 0 < alpha <= 2 (paper: 1 < alpha <= 2)
+ *   kappa[S]  diffusion coefficient per species, >= 0
+ *   dt        time step tau > 0
+ *   reaction  enum sfrde_reaction; nparams must match it, params[nparams]
+ *   dtype     SFRDE_F32 or SFRDE_F64: the type of fields and of the
+ *             transforms; eigenvalues and coefficients are always computed
+ *             in FP64 and stored in dtype
+ *   scheme    SFRDE_SCHEME_P13 (the paper's) or SFRDE_SCHEME_EXP
+ *   hip_stream  hipStream_t to enqueue on (NULL: the default stream)
+ * Errors: EINVAL for any argument outside the ranges above (no device call is
+ * made), ENOMEM/EDEVICE from the device. */
+int sfrde_plan(sfrde_plan_t* out, int32_t ndim, const int64_t* n, int32_t bc,
+               const double* h, int32_t nspecies, const double* alpha,
+               const double* kappa, double dt, int32_t reaction, int32_t nparams,
+               const double* params, int32_t dtype, int32_t scheme, void* hip_stream);
+
+/* One step from time t (eq. ETDRK4P13): state <- u(t + dt), in place.
+ * state: device [S][...] of the plan's dtype. Same as sfrde_integrate with
+ * nsteps = 1 and no checkpoints. */
+int sfrde_step(sfrde_plan_t plan, void* state, double t);
+
+/* nsteps steps from t0, in place on state (Alg. 1 time loop). If ckpt_every
+ * > 0 and ckpt != NULL, the spectral state before steps 0, K, 2K, ...
+ * (K = ckpt_every) is stored in ckpt (device, sfrde_ckpt_bytes() bytes),
+ * which sfrde_backward and sfrde_resume read. nsteps = 0 leaves state
+ * untouched. Returns SFRDE_ENONFINITE (state then holds the non-finite
+ * result) if any stage produced NaN/Inf. */
+int sfrde_integrate(sfrde_plan_t plan, void* state, int64_t nsteps, double t0,
+                    int64_t ckpt_every, void* ckpt);
+
+/* Bytes of the checkpoint buffer for (nsteps, ckpt_every): a
+ * SFRDE_CKPT_HEADER_BYTES header plus ceil(nsteps/ckpt_every) spectral
+ * states. Negative sfrde_status on bad arguments. */
+int64_t sfrde_ckpt_bytes(sfrde_plan_t plan, int64_t nsteps, int64_t ckpt_every);
+
+/* Continue from checkpoint slot `slot` (the spectral state before step
+ * slot*K of the run that wrote ckpt): runs nsteps steps from t0 into state.
+ * Bitwise identical to the original run's continuation. ckpt_out as in
+ * sfrde_integrate (may be NULL). */
+int sfrde_resume(sfrde_plan_t plan, const void* ckpt, int64_t slot, void* state,
+                 int64_t nsteps, double t0, int64_t ckpt_every, void* ckpt_out);
+
+/* Discrete adjoint of nsteps steps (the reverse sweep of eq. ETDRK4P13 with
+ * transposed transforms, the same diagonal coefficients and the reaction
+ * Jacobian transposed). ckpt must come from sfrde_integrate(nsteps, t0,
+ * ckpt_every) with this plan's shape, dtype and species count. Segments of
+ * ckpt_every steps are recomputed from their checkpoint (memory: about
+ * 9 * ckpt_every fields of workspace).
+ *   grad_uT     device [S][...] dtype: dLoss/du(T)
+ *   grad_u0     device [S][...] dtype: receives dLoss/du(0) (NULL: skip)
+ *   grad_kappa  host double[S] (NULL: skip)   dLoss/dkappa_s
+ *   grad_alpha  host double[S] (NULL: skip)   dLoss/dalpha_s
+ *   grad_params host double[nparams] (NULL: skip)
+ * Errors: ESTATE if the checkpoint does not match. */
+int sfrde_backward(sfrde_plan_t plan, const void* ckpt, int64_t nsteps,
+                   int64_t ckpt_every, double t0, const void* grad_uT, void* grad_u0,
+                   double* grad_kappa, double* grad_alpha, double* grad_params);
+
+/* Free the plan and everything it owns (waits for its stream first). */
+int sfrde_destroy(sfrde_plan_t plan);
+
+/* Message for the last non-OK return on this thread ("" if none). */
+const char* sfrde_last_error(void);
+
+/* Device bytes owned by the plan (tables and workspace) right now. */
+int64_t sfrde_workspace_bytes(sfrde_plan_t plan);
+
+/* Measurement. sfrde_profile(plan, k) with k >= 1 clears the record, makes
+ * events for k launches up front, and brackets every later kernel launch of
+ * the plan with HIP events on its stream (more are made if needed);
+ * sfrde_profile(plan, 0) stops recording. sfrde_profile_read synchronizes
+ * the stream and returns, per kernel class, the summed event time in ms and
+ * the launch count (arrays of SFRDE_K_COUNT entries). */
+enum sfrde_kernel_class {
+  SFRDE_K_X = 0,     /* inverse-x, reaction, forward-x */
+  SFRDE_K_Y = 1,     /* single-axis transform passes */
+  SFRDE_K_Z = 2,     /* forward, stage combine, inverse along the last axis */
+  SFRDE_K_XADJ = 3,  /* adjoint X */
+  SFRDE_K_ZADJ = 4,  /* adjoint Z */
+  SFRDE_K_OTHER = 5,
+  SFRDE_K_COUNT = 6
+};
+int sfrde_profile(sfrde_plan_t plan, int32_t enable);
+int sfrde_profile_read(sfrde_plan_t plan, double* ms, int64_t* launches);
+
+/* Host-only helpers (no device needed), for checks of the plan's tables:
+ * the per-axis eigenvalues (Section 3.1) in the library's spectral order, and
+ * the six coefficients (R, Q, phi, phi1, phi2, phi3) at one L >= 0 or their
+ * derivatives d/dL (deriv != 0). */
+int sfrde_axis_eigenvalues(int32_t bc, int64_t n, double h, double* out);
+int sfrde_eval_coefficients(int32_t scheme, double L, double dt, int32_t deriv,
+                            double* out6);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,602 @@
+// Device kernels of the ETDRK4 step.
+//
+// Every field is [S][total] with x fastest. A kernel works on "line tiles":
+// W lines along one axis (length n, stride `inner`), staged in LDS as
+// buf[s][j][w] (j along the axis, w the line within the tile). Per-axis
+// transforms are products with the axis matrix M (forward, unnormalised):
+//   periodic  M[k][j] = cos(2 pi kj/N) + sin(2 pi kj/N)   (discrete Hartley)
+//   Dirichlet M[k][j] = sin(pi (k+1)(j+1)/N)                (DST-I)
+//   Neumann   M[k][j] = cos(pi kj/N) w_j, w = 1/2 at both ends (DCT-I)
+// and the inverse along an axis is the same product scaled by 1/N, 2/N, 2/N;
+// these scales are folded into the stage combine (one factor `cs` for all
+// axes), so forward and inverse use identical arithmetic.
+//
+// One stage of eq. ETDRK4P13 in 3D is four kernels on one buffer P:
+//   X: inverse-x, reaction f(stage value), forward-x
+//   Y: forward-y
+//   Z: forward-z, diagonal combine with the retained spectral arrays, inverse-z
+//   Y: inverse-y
+// (2D drops the Y passes). The combine keeps u_hat (spectral state), c_til
+// and acc across the stages so that a and 2 f_b - f_u are never transformed
+// again (linearity of the transforms):
+//   st 0: a = Q u + phi f_u; c_til = Q a - phi f_u; acc = R u + phi1 f_u
+//   st 1: b = Q u + phi f_a; acc += phi2 f_a
+//   st 2: c = c_til + 2 phi f_b; acc += phi2 f_b
+//   st 3: u_hat = acc + phi3 f_c
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "coef.h"
+#include "reactions.h"
+
+namespace sfrde {
+
+constexpr int NTHREADS = 256;
+constexpr int KMAX = 32;  // outputs per thread in the dense transform: n*W <= KMAX*NTHREADS
+
+struct Geom {
+  int n;            // length of the transformed axis
+  int W;            // lines per tile
+  int pitch;        // LDS row pitch (>= W)
+  int pad_;
+  long long inner;  // stride of the axis (1 for x)
+  long long outer;  // lines (inner == 1) or outer blocks of n*inner
+  long long tpo;    // tiles per outer block (inner > 1)
+  long long ntiles;
+  long long total;  // points per species
+};
+
+// Global index of element (j, w) of a tile; false for lanes past the edge.
+__device__ __forceinline__ bool elem(const Geom& g, long long tile, int j, int w, long long& idx) {
+  if (g.inner == 1) {
+    long long line = tile * g.W + w;
+    idx = line * g.n + j;
+    return line < g.outer;
+  }
+  long long o = tile / g.tpo;
+  long long i = (tile - o * g.tpo) * g.W + w;
+  idx = o * (long long)g.n * g.inner + (long long)j * g.inner + i;
+  return i < g.inner;
+}
+
+// Element e of the tile in coalescing order: consecutive threads touch
+// consecutive global addresses.
+__device__ __forceinline__ void unpack(const Geom& g, int e, int& j, int& w) {
+  if (g.inner == 1) {
+    w = e / g.n;
+    j = e - w * g.n;
+  } else {
+    j = e / g.W;
+    w = e - j * g.W;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_tile(const Geom& g, long long tile, const T* __restrict__ src,
+                                          T* buf, int S) {
+  const int ne = g.n * g.W;
+  for (int s = 0; s < S; ++s) {
+    const T* sp = src + (long long)s * g.total;
+    T* b = buf + s * g.n * g.pitch;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      int j, w;
+      unpack(g, e, j, w);
+      long long idx;
+      b[j * g.pitch + w] = elem(g, tile, j, w, idx) ? sp[idx] : T(0);
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_tile(const Geom& g, long long tile, const T* buf,
+                                           T* __restrict__ dst, int S) {
+  const int ne = g.n * g.W;
+  for (int s = 0; s < S; ++s) {
+    T* dp = dst + (long long)s * g.total;
+    const T* b = buf + s * g.n * g.pitch;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      int j, w;
+      unpack(g, e, j, w);
+      long long idx;
+      if (elem(g, tile, j, w, idx)) dp[idx] = b[j * g.pitch + w];
+    }
+  }
+}
+
+// In-place dense transform of every species' tile: b[k][w] <- sum_j M[k][j] b[j][w].
+// Mt is the transposed matrix (Mt[j*n + k] = M[k][j]) so that the threads of
+// a wave read consecutive k.
+template <typename T>
+__device__ __forceinline__ void dense_transform(T* buf, int S, const Geom& g,
+                                                const T* __restrict__ Mt) {
+  const int W = g.W, n = g.n, pitch = g.pitch;
+  const int KG = blockDim.x / W;
+  const int w = threadIdx.x % W, kg = threadIdx.x / W;
+  for (int s = 0; s < S; ++s) {
+    T* b = buf + s * n * pitch;
+    T acc[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) acc[q] = T(0);
+    for (int j = 0; j < n; ++j) {
+      const T v = b[j * pitch + w];
+      const T* mr = Mt + (long long)j * n + kg;
+#pragma unroll
+      for (int q = 0; q < KMAX; ++q) {
+        if (kg + q * KG < n) acc[q] += mr[q * KG] * v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) {
+      const int k = kg + q * KG;
+      if (k < n) b[k * pitch + w] = acc[q];
+    }
+    __syncthreads();
+  }
+}
+
+// Per-point weight of the Neumann pencil (1/2 per axis at a boundary node).
+__device__ __forceinline__ double point_weight(long long idx, long long n0, long long n1,
+                                               long long n2) {
+  long long i0 = idx % n0;
+  long long r = idx / n0;
+  long long i1 = r % n1;
+  long long i2 = r / n1;
+  double w = 1.0;
+  if (i0 == 0 || i0 == n0 - 1) w *= 0.5;
+  if (i1 == 0 || i1 == n1 - 1) w *= 0.5;
+  if (n2 > 1 && (i2 == 0 || i2 == n2 - 1)) w *= 0.5;
+  return w;
+}
+
+// --------------------------------------------------------------------------
+enum { MODE_INIT = 4, MODE_RESTORE = 5 };
+
+template <typename T>
+struct StageArgs {
+  Geom g;
+  const T* Mt;
+  T* P;             // in/out fields [S][total]
+  const T* src;     // Z kernel: load from here and skip the forward transform
+  const T* coef;    // [6][S][total]
+  const T* dcoef;   // [6][S][total] (adjoint parameter sensitivities)
+  T* uhat;          // forward retained arrays
+  T* ctil;
+  T* acc;
+  T* zh;            // adjoint retained arrays
+  T* aacc;
+  T* ahat;
+  T* gu;
+  double* G;        // [S][total] L-sensitivity accumulator
+  T* st_phys;       // stored stage values of this step [4][S][total]
+  T* st_uhat;       // stored spectral state of this step [S][total]
+  T* st_fhat;       // stored transformed reactions [4][S][total]
+  double* rp_acc;   // [np][gridDim.x] reaction-parameter accumulators
+  int* flag;        // set to 1 on a non-finite value
+  Rxn rxn;
+  double t;
+  T cs;             // product of the per-axis inverse scales
+  int S;
+  int mode;         // stage 0..3, or MODE_INIT / MODE_RESTORE
+  int last;         // adjoint: this is step 0 (output u-bar, not phi3 u-bar)
+  int neumann;
+  long long n0, n1, n2;
+};
+
+// X kernel, forward: inverse-x, reaction, forward-x (in place on P).
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_xstage(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* buf = reinterpret_cast<T*>(smem_raw);
+  const Geom& g = a.g;
+  const long long tile = blockIdx.x;
+  const int S = a.S;
+  load_tile(g, tile, a.P, buf, S);
+  __syncthreads();
+  dense_transform(buf, S, g, a.Mt);
+  bool bad = false;
+  const int ne = g.n * g.W;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    int j, w;
+    unpack(g, e, j, w);
+    long long idx;
+    if (!elem(g, tile, j, w, idx)) continue;
+    T u[MAX_SPECIES], f[MAX_SPECIES];
+    for (int s = 0; s < S; ++s) u[s] = buf[(s * g.n + j) * g.pitch + w];
+    if (a.st_phys) {
+      for (int s = 0; s < S; ++s) a.st_phys[((long long)a.mode * S + s) * g.total + idx] = u[s];
+    }
+    rxn_eval(a.rxn, u, f);
+    for (int s = 0; s < S; ++s) {
+      bad |= !isfinite(u[s]) || !isfinite(f[s]);
+      buf[(s * g.n + j) * g.pitch + w] = f[s];
+    }
+  }
+  if (bad) a.flag[0] = 1;
+  __syncthreads();
+  dense_transform(buf, S, g, a.Mt);
+  store_tile(g, tile, buf, a.P, S);
+}
+
+// Z kernel, forward: forward transform along the last axis, stage combine,
+// inverse transform (in place on P).
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* buf = reinterpret_cast<T*>(smem_raw);
+  const Geom& g = a.g;
+  const long long tile = blockIdx.x;
+  const int S = a.S;
+  load_tile(g, tile, a.src ? a.src : a.P, buf, S);
+  __syncthreads();
+  if (!a.src) dense_transform(buf, S, g, a.Mt);
+  const int ne = g.n * g.W;
+  const long long tot = g.total;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    int j, w;
+    unpack(g, e, j, w);
+    long long idx;
+    if (!elem(g, tile, j, w, idx)) continue;
+    for (int s = 0; s < S; ++s) {
+      T& cell = buf[(s * g.n + j) * g.pitch + w];
+      const T fh = cell;
+      const long long i = s * tot + idx;
+      const T* cf = a.coef + i;  // coefficient q at cf[q * S * tot]
+      const long long cst = (long long)S * tot;
+      T out;
+      switch (a.mode) {
+        case 0: {
+          const T uh = a.uhat[i];
+          if (a.st_uhat) a.st_uhat[i] = uh;
+          if (a.st_fhat) a.st_fhat[0 * S * tot + i] = fh;
+          const T cQ = cf[C_Q * cst], cP = cf[C_PHI * cst];
+          const T av = cQ * uh + cP * fh;
+          a.ctil[i] = cQ * av - cP * fh;
+          a.acc[i] = cf[C_R * cst] * uh + cf[C_PHI1 * cst] * fh;
+          out = av;
+          break;
+        }
+        case 1: {
+          if (a.st_fhat) a.st_fhat[1 * S * tot + i] = fh;
+          const T uh = a.uhat[i];
+          out = cf[C_Q * cst] * uh + cf[C_PHI * cst] * fh;
+          a.acc[i] += cf[C_PHI2 * cst] * fh;
+          break;
+        }
+        case 2: {
+          if (a.st_fhat) a.st_fhat[2 * S * tot + i] = fh;
+          const T cP = cf[C_PHI * cst];
+          out = a.ctil[i] + T(2) * cP * fh;
+          a.acc[i] += cf[C_PHI2 * cst] * fh;
+          break;
+        }
+        case 3: {
+          if (a.st_fhat) a.st_fhat[3 * S * tot + i] = fh;
+          const T un = a.acc[i] + cf[C_PHI3 * cst] * fh;
+          a.uhat[i] = un;
+          out = un;
+          break;
+        }
+        case MODE_INIT:
+          a.uhat[i] = fh;
+          out = fh;
+          break;
+        default:  // MODE_RESTORE: src is the spectral state
+          out = fh;
+          break;
+      }
+      cell = a.cs * out;
+    }
+  }
+  __syncthreads();
+  dense_transform(buf, S, g, a.Mt);
+  store_tile(g, tile, buf, a.P, S);
+}
+
+// X kernel, adjoint: inverse-x of the spectral cotangent of f(stage value),
+// multiply by the transposed reaction Jacobian at the stored stage value,
+// forward-x. Accumulates the reaction-parameter gradient per block.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* buf = reinterpret_cast<T*>(smem_raw);
+  const Geom& g = a.g;
+  const long long tile = blockIdx.x;
+  const int S = a.S;
+  const bool want_p = a.rp_acc != nullptr;
+  load_tile(g, tile, a.P, buf, S);
+  __syncthreads();
+  dense_transform(buf, S, g, a.Mt);
+  double pacc[MAX_PARAMS];
+  for (int k = 0; k < MAX_PARAMS; ++k) pacc[k] = 0.0;
+  const int ne = g.n * g.W;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    int j, w;
+    unpack(g, e, j, w);
+    long long idx;
+    if (!elem(g, tile, j, w, idx)) continue;
+    T u[MAX_SPECIES], gg[MAX_SPECIES], o[MAX_SPECIES];
+    for (int s = 0; s < S; ++s) {
+      gg[s] = buf[(s * g.n + j) * g.pitch + w];
+      u[s] = a.st_phys[((long long)a.mode * S + s) * g.total + idx];
+    }
+    const double wgt = a.neumann ? point_weight(idx, a.n0, a.n1, a.n2) : 1.0;
+    rxn_adjoint(a.rxn, u, gg, o, wgt, pacc, want_p);
+    for (int s = 0; s < S; ++s) buf[(s * g.n + j) * g.pitch + w] = o[s];
+  }
+  __syncthreads();
+  dense_transform(buf, S, g, a.Mt);
+  store_tile(g, tile, buf, a.P, S);
+  if (want_p) {
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem_raw);
+    for (int k = 0; k < a.rxn.np; ++k) {
+      red[threadIdx.x] = pacc[k];
+      __syncthreads();
+      for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) a.rp_acc[(long long)k * gridDim.x + blockIdx.x] += red[0];
+      __syncthreads();
+    }
+  }
+}
+
+// Z kernel, adjoint: forward-z of J^T(...) (the cotangent of a stage's
+// spectral value), the adjoint combine, inverse-z. Cotangents are carried in
+// the variables for which the transposed transforms are the forward ones
+// (physical cotangents divided by the Neumann point weights, spectral ones
+// by the inverse scale and spectral weights). With z = cotangent of the
+// step output and X the incoming term of each stage:
+//   st 0 (c): aacc = R z; ahat = Q X; gu = phi1 z - phi X; out = phi2 z + 2 phi X
+//   st 1 (b): aacc += Q X; out = phi2 z + phi X
+//   st 2 (a): A = ahat + X; aacc += Q A; out = gu + phi A
+//   st 3 (u): z <- aacc + X; out = phi3 z (or z itself at the first step)
+// G accumulates, per mode, y * g'(L) * x over every coefficient application
+// y_out = g(L) x of the forward step, for the kappa and alpha gradients.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_zadj(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* buf = reinterpret_cast<T*>(smem_raw);
+  const Geom& g = a.g;
+  const long long tile = blockIdx.x;
+  const int S = a.S;
+  load_tile(g, tile, a.P, buf, S);
+  __syncthreads();
+  dense_transform(buf, S, g, a.Mt);
+  const int ne = g.n * g.W;
+  const long long tot = g.total;
+  const long long cst = (long long)S * tot;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    int j, w;
+    unpack(g, e, j, w);
+    long long idx;
+    if (!elem(g, tile, j, w, idx)) continue;
+    for (int s = 0; s < S; ++s) {
+      T& cell = buf[(s * g.n + j) * g.pitch + w];
+      const T X = cell;
+      const long long i = s * tot + idx;
+      const T* cf = a.coef + i;
+      const T* dc = a.dcoef ? a.dcoef + i : nullptr;
+      T out;
+      switch (a.mode) {
+        case 0: {
+          const T z = a.zh[i];
+          const T cQ = cf[C_Q * cst], cP = cf[C_PHI * cst];
+          a.aacc[i] = cf[C_R * cst] * z;
+          a.ahat[i] = cQ * X;
+          a.gu[i] = cf[C_PHI1 * cst] * z - cP * X;
+          out = cf[C_PHI2 * cst] * z + T(2) * cP * X;
+          if (a.G) {
+            const T uh = a.st_uhat[i];
+            const T fu = a.st_fhat[0 * cst + i], fa = a.st_fhat[1 * cst + i];
+            const T fb = a.st_fhat[2 * cst + i], fc = a.st_fhat[3 * cst + i];
+            const T ah = cQ * uh + cP * fu;
+            const T s1 = dc[C_R * cst] * uh + dc[C_PHI1 * cst] * fu +
+                         dc[C_PHI2 * cst] * (fa + fb) + dc[C_PHI3 * cst] * fc;
+            const T s2 = dc[C_Q * cst] * ah + dc[C_PHI * cst] * (T(2) * fb - fu);
+            a.G[i] += double(z) * double(s1) + double(X) * double(s2);
+          }
+          break;
+        }
+        case 1: {
+          const T z = a.zh[i];
+          a.aacc[i] += cf[C_Q * cst] * X;
+          out = cf[C_PHI2 * cst] * z + cf[C_PHI * cst] * X;
+          if (a.G) {
+            const T uh = a.st_uhat[i], fa = a.st_fhat[1 * cst + i];
+            a.G[i] += double(X) * double(dc[C_Q * cst] * uh + dc[C_PHI * cst] * fa);
+          }
+          break;
+        }
+        case 2: {
+          const T A = a.ahat[i] + X;
+          a.aacc[i] += cf[C_Q * cst] * A;
+          out = a.gu[i] + cf[C_PHI * cst] * A;
+          if (a.G) {
+            const T uh = a.st_uhat[i], fu = a.st_fhat[0 * cst + i];
+            a.G[i] += double(A) * double(dc[C_Q * cst] * uh + dc[C_PHI * cst] * fu);
+          }
+          break;
+        }
+        case 3: {
+          const T zn = a.aacc[i] + X;
+          a.zh[i] = zn;
+          out = a.last ? zn : cf[C_PHI3 * cst] * zn;
+          break;
+        }
+        default:  // MODE_INIT: X is the transformed cotangent of u(T)
+          a.zh[i] = X;
+          out = cf[C_PHI3 * cst] * X;
+          break;
+      }
+      cell = a.cs * out;
+    }
+  }
+  __syncthreads();
+  dense_transform(buf, S, g, a.Mt);
+  store_tile(g, tile, buf, a.P, S);
+}
+
+// One transform along one axis, src -> dst (may alias), with optional
+// Neumann point weights before (divide) or after (multiply).
+template <typename T>
+struct SingleArgs {
+  Geom g;
+  const T* Mt;
+  const T* src;
+  T* dst;
+  int S;
+  int pre_divide_w;
+  int post_multiply_w;
+  int pad_;
+  long long n0, n1, n2;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* buf = reinterpret_cast<T*>(smem_raw);
+  const Geom& g = a.g;
+  const long long tile = blockIdx.x;
+  load_tile(g, tile, a.src, buf, a.S);
+  __syncthreads();
+  const int ne = g.n * g.W;
+  if (a.pre_divide_w) {
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      int j, w;
+      unpack(g, e, j, w);
+      long long idx;
+      if (!elem(g, tile, j, w, idx)) continue;
+      const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
+      for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] /= wt;
+    }
+    __syncthreads();
+  }
+  dense_transform(buf, a.S, g, a.Mt);
+  if (a.post_multiply_w) {
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+      int j, w;
+      unpack(g, e, j, w);
+      long long idx;
+      if (!elem(g, tile, j, w, idx)) continue;
+      const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
+      for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] *= wt;
+    }
+    __syncthreads();
+  }
+  store_tile(g, tile, buf, a.dst, a.S);
+}
+
+// --------------------------------------------------------------------------
+// Plan-time coefficient tables in FP64 (Alg. 1 precompute), stored in T:
+// out[q][s][idx] for the six functions of L = kappa_s tau Lambda^(alpha_s/2),
+// Lambda = lam0[i0] + lam1[i1] + lam2[i2], or their d/dL when deriv != 0.
+struct CoefArgs {
+  const double* lam0;
+  const double* lam1;
+  const double* lam2;
+  long long n0, n1, n2, total;
+  int S;
+  int scheme;
+  int deriv;
+  int pad_;
+  double tau;
+  double alpha[MAX_SPECIES];
+  double kappa[MAX_SPECIES];
+};
+
+__device__ __forceinline__ double lambda_at(const CoefArgs& c, long long idx) {
+  long long i0 = idx % c.n0;
+  long long r = idx / c.n0;
+  long long i1 = r % c.n1;
+  long long i2 = r / c.n1;
+  double lam = c.lam0[i0] + c.lam1[i1];
+  if (c.n2 > 1) lam += c.lam2[i2];
+  return lam;
+}
+
+template <typename T>
+__global__ void k_coefs(CoefArgs c, T* out) {
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < c.total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const double lam = lambda_at(c, idx);
+    for (int s = 0; s < c.S; ++s) {
+      const double L = lam > 0.0 ? c.kappa[s] * c.tau * pow(lam, 0.5 * c.alpha[s]) : 0.0;
+      double v[NCOEF];
+      if (c.deriv)
+        coef_derivs(c.scheme, L, c.tau, v);
+      else
+        coef_values(c.scheme, L, c.tau, v);
+      for (int q = 0; q < NCOEF; ++q) out[((long long)q * c.S + s) * c.total + idx] = T(v[q]);
+    }
+  }
+}
+
+// kappa/alpha gradients from the per-mode sensitivities G:
+// part[q][block], q = 2s (kappa_s) and 2s+1 (alpha_s), of
+// sum_k omega_k G_k dL_k/dtheta with dL/dkappa = tau Lambda^(alpha/2),
+// dL/dalpha = L ln(Lambda)/2 and omega_k = cs * (Neumann spectral weights).
+__global__ void k_greduce(CoefArgs c, const double* G, double cs, int neumann, double* part) {
+  __shared__ double red[NTHREADS];
+  double acc[2 * MAX_SPECIES];
+  for (int q = 0; q < 2 * MAX_SPECIES; ++q) acc[q] = 0.0;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < c.total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    const double lam = lambda_at(c, idx);
+    if (!(lam > 0.0)) continue;
+    const double om = cs * (neumann ? point_weight(idx, c.n0, c.n1, c.n2) : 1.0);
+    const double lnl = log(lam);
+    for (int s = 0; s < c.S; ++s) {
+      const double pw = pow(lam, 0.5 * c.alpha[s]);
+      const double gk = om * G[(long long)s * c.total + idx];
+      acc[2 * s] += gk * c.tau * pw;
+      acc[2 * s + 1] += gk * 0.5 * c.kappa[s] * c.tau * pw * lnl;
+    }
+  }
+  for (int q = 0; q < 2 * c.S; ++q) {
+    red[threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long long)q * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[r] = sum over in[r][0..len) in a fixed order (one block per row).
+__global__ void k_rowsum(const double* in, long long len, double* out) {
+  __shared__ double red[NTHREADS];
+  const double* row = in + blockIdx.x * len;
+  double a = 0.0;
+  for (long long i = threadIdx.x; i < len; i += blockDim.x) a += row[i];
+  red[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+template <typename T>
+__global__ void k_fill(T* p, long long n, T v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Checkpoint header: eight 64-bit words, lane i writes word i.
+__global__ void k_header(long long* h, long long a0, long long a1, long long a2, long long a3,
+                         long long a4, long long a5, long long a6, long long a7) {
+  const int i = threadIdx.x;
+  const long long v = i == 0 ? a0 : i == 1 ? a1 : i == 2 ? a2 : i == 3 ? a3
+                    : i == 4 ? a4 : i == 5 ? a5 : i == 6 ? a6 : a7;
+  if (blockIdx.x == 0 && i < 8) h[i] = v;
+}
+
+}  // namespace sfrde

@@ -1,0 +1,131 @@
+// Pointwise reaction terms of the pattern models (Section 5.2), their
+// transposed Jacobians and parameter partials, in the field precision T.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sfrde {
+
+enum { RXN_LINEAR = 0, RXN_FHN = 1, RXN_GRAY_SCOTT = 2, RXN_SCHNAKENBERG = 3, RXN_GM = 4 };
+constexpr int MAX_SPECIES = 4;
+constexpr int MAX_PARAMS = 16;
+
+struct Rxn {
+  int kind;
+  int S;
+  int np;
+  double p[MAX_PARAMS];
+};
+
+// f = f(u); u and f hold S values.
+template <typename T>
+__device__ __forceinline__ void rxn_eval(const Rxn& r, const T* u, T* f) {
+  switch (r.kind) {
+    case RXN_LINEAR:
+      for (int s = 0; s < r.S; ++s) f[s] = T(r.p[s]) * u[s];
+      break;
+    case RXN_FHN: {
+      const T mu = T(r.p[0]), eps = T(r.p[1]), beta = T(r.p[2]), gam = T(r.p[3]), dlt = T(r.p[4]);
+      const T x = u[0], v = u[1];
+      f[0] = x * (T(1) - x) * (x - mu) - v;
+      f[1] = eps * (beta * x - gam * v - dlt);
+      break;
+    }
+    case RXN_GRAY_SCOTT: {
+      const T F = T(r.p[0]), K = T(r.p[1]);
+      const T x = u[0], v = u[1];
+      const T xvv = x * v * v;
+      f[0] = -xvv + F * (T(1) - x);
+      f[1] = xvv - (F + K) * v;
+      break;
+    }
+    case RXN_SCHNAKENBERG: {
+      const T g = T(r.p[0]), a = T(r.p[1]), b = T(r.p[2]);
+      const T x = u[0], v = u[1];
+      const T xxv = x * x * v;
+      f[0] = g * (a - x + xxv);
+      f[1] = g * (b - xxv);
+      break;
+    }
+    default: {  // Gierer-Meinhardt
+      const T rho = T(r.p[0]), mu_u = T(r.p[1]), s_u = T(r.p[2]), s_v = T(r.p[3]), mu_v = T(r.p[4]);
+      const T x = u[0], v = u[1];
+      f[0] = rho - mu_u * x + s_u * x * x / v;
+      f[1] = s_v * x * x - mu_v * v;
+      break;
+    }
+  }
+}
+
+// out = J_f(u)^T g (out_r = sum_s g_s d f_s / d u_r), and
+// pacc[k] += wgt * sum_s g_s d f_s / d p_k.
+template <typename T>
+__device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g, T* out,
+                                            double wgt, double* pacc, bool want_p) {
+  switch (r.kind) {
+    case RXN_LINEAR:
+      for (int s = 0; s < r.S; ++s) {
+        out[s] = T(r.p[s]) * g[s];
+        if (want_p) pacc[s] += wgt * double(g[s] * u[s]);
+      }
+      break;
+    case RXN_FHN: {
+      const T mu = T(r.p[0]), eps = T(r.p[1]), beta = T(r.p[2]), gam = T(r.p[3]), dlt = T(r.p[4]);
+      const T x = u[0], v = u[1], gu = g[0], gv = g[1];
+      const T dfu_du = -T(3) * x * x + T(2) * (T(1) + mu) * x - mu;
+      out[0] = gu * dfu_du + gv * eps * beta;
+      out[1] = -gu - gv * eps * gam;
+      if (want_p) {
+        pacc[0] += wgt * double(gu * (-x * (T(1) - x)));
+        pacc[1] += wgt * double(gv * (beta * x - gam * v - dlt));
+        pacc[2] += wgt * double(gv * eps * x);
+        pacc[3] += wgt * double(-gv * eps * v);
+        pacc[4] += wgt * double(-gv * eps);
+      }
+      break;
+    }
+    case RXN_GRAY_SCOTT: {
+      const T F = T(r.p[0]), K = T(r.p[1]);
+      const T x = u[0], v = u[1], gu = g[0], gv = g[1];
+      const T xv2 = T(2) * x * v;
+      out[0] = gu * (-v * v - F) + gv * v * v;
+      out[1] = gu * (-xv2) + gv * (xv2 - F - K);
+      if (want_p) {
+        pacc[0] += wgt * double(gu * (T(1) - x) - gv * v);
+        pacc[1] += wgt * double(-gv * v);
+      }
+      break;
+    }
+    case RXN_SCHNAKENBERG: {
+      const T gm = T(r.p[0]), a = T(r.p[1]), b = T(r.p[2]);
+      const T x = u[0], v = u[1], gu = g[0], gv = g[1];
+      const T xv2 = T(2) * x * v, xx = x * x;
+      out[0] = gm * (gu * (xv2 - T(1)) - gv * xv2);
+      out[1] = gm * (gu - gv) * xx;
+      if (want_p) {
+        const T xxv = xx * v;
+        pacc[0] += wgt * double(gu * (a - x + xxv) + gv * (b - xxv));
+        pacc[1] += wgt * double(gu * gm);
+        pacc[2] += wgt * double(gv * gm);
+      }
+      break;
+    }
+    default: {  // Gierer-Meinhardt
+      const T mu_u = T(r.p[1]), s_u = T(r.p[2]), s_v = T(r.p[3]), mu_v = T(r.p[4]);
+      const T x = u[0], v = u[1], gu = g[0], gv = g[1];
+      const T xv = x / v;
+      out[0] = gu * (-mu_u + T(2) * s_u * xv) + gv * T(2) * s_v * x;
+      out[1] = -gu * s_u * xv * xv - gv * mu_v;
+      if (want_p) {
+        pacc[0] += wgt * double(gu);
+        pacc[1] += wgt * double(-gu * x);
+        pacc[2] += wgt * double(gu * x * xv);
+        pacc[3] += wgt * double(gv * x * x);
+        pacc[4] += wgt * double(-gv * v);
+      }
+      break;
+    }
+  }
+}
+
+}  // namespace sfrde

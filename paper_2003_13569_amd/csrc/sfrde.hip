@@ -1,0 +1,929 @@
+// libsfrde: host plan, step drivers and the C ABI declared in include/sfrde.h.
+//
+// A plan holds, on the device: per-axis transform matrices (dtype, built in
+// FP64 on the host from the closed forms of Section 3.1), per-axis FP64
+// eigenvalue tables, the six coefficient tables of the Alg. 1 precompute
+// (computed in FP64 on the device, stored in dtype), and the workspace of the
+// step: one field buffer P that every kernel transforms in place, and the
+// retained spectral arrays u_hat, c_til, acc. The backward pass adds the
+// adjoint buffers, a segment store for recomputed stage data and the
+// derivative tables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sfrde.h"
+#include "coef.h"
+#include "kernels.h"
+
+using namespace sfrde;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHECK(expr)                                                                  \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? SFRDE_ENOMEM : SFRDE_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+#define TRY(expr)              \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != SFRDE_OK) return rc_; \
+  } while (0)
+
+const long long CKPT_MAGIC = 0x5346524445434b31LL;  // "SFRDECK1"
+constexpr int MAX_N = 1024;
+
+}  // namespace
+
+struct sfrde_plan_s {
+  int ndim = 0;
+  long long n[3] = {1, 1, 1};
+  int bc = 0;
+  double h[3] = {1, 1, 1};
+  int S = 0;
+  double alpha[MAX_SPECIES] = {0};
+  double kappa[MAX_SPECIES] = {0};
+  double dt = 0;
+  Rxn rxn{};
+  int dtype = 0;
+  int scheme = 0;
+  hipStream_t stream = nullptr;
+  long long total = 0;
+  double cs = 1;  // product of per-axis inverse scales
+  size_t w = 4;   // bytes per real
+  Geom geom[3]{};
+  size_t lds[3] = {0, 0, 0};
+  // device memory
+  void* Mt[3] = {nullptr, nullptr, nullptr};
+  double* lam[3] = {nullptr, nullptr, nullptr};
+  void* coef = nullptr;
+  void* dcoef = nullptr;
+  void* P = nullptr;
+  void* uhat = nullptr;
+  void* ctil = nullptr;
+  void* acc = nullptr;
+  void* Pa = nullptr;
+  void* zh = nullptr;
+  void* aacc = nullptr;
+  void* ahat = nullptr;
+  void* gu = nullptr;
+  double* G = nullptr;
+  void* seg = nullptr;
+  long long seg_steps = 0;
+  double* rp_acc = nullptr;
+  double* red = nullptr;  // reduction scratch
+  long long red_len = 0;
+  int* flag = nullptr;
+  int* h_flag = nullptr;  // pinned host mirror
+  size_t bytes = 0;
+  // measurement: optional HIP events around every kernel launch
+  bool prof = false;
+  std::vector<hipEvent_t> ev;    // start/stop pairs
+  std::vector<int> ev_class;     // kernel class per pair
+  size_t ev_used = 0;            // pairs recorded since the last reset
+};
+
+namespace {
+
+size_t field_bytes(const sfrde_plan_s* p) { return (size_t)p->S * p->total * p->w; }
+
+int dev_alloc(sfrde_plan_s* p, void** ptr, size_t bytes) {
+  if (*ptr) return SFRDE_OK;
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    return fail(e == hipErrorOutOfMemory ? SFRDE_ENOMEM : SFRDE_EDEVICE,
+                "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  p->bytes += bytes;
+  return SFRDE_OK;
+}
+
+void dev_free(sfrde_plan_s* p, void** ptr, size_t bytes) {
+  if (*ptr) {
+    (void)hipFree(*ptr);
+    p->bytes -= bytes;
+    *ptr = nullptr;
+  }
+}
+
+// Kernel classes for measurement (enum order of SFRDE_K_* in sfrde.h).
+enum { KC_X = 0, KC_Y = 1, KC_Z = 2, KC_XADJ = 3, KC_ZADJ = 4, KC_OTHER = 5, KC_COUNT = 6 };
+
+// Record the start event of a measured launch; returns the pair index or -1.
+long long prof_start(sfrde_plan_s* p, int cls) {
+  if (!p->prof) return -1;
+  const size_t k = p->ev_used;
+  while (p->ev.size() < 2 * (k + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    p->ev.push_back(e);
+  }
+  if (p->ev_class.size() < k + 1) p->ev_class.resize(k + 1);
+  p->ev_class[k] = cls;
+  if (hipEventRecord(p->ev[2 * k], p->stream) != hipSuccess) return -1;
+  p->ev_used = k + 1;
+  return (long long)k;
+}
+
+void prof_stop(sfrde_plan_s* p, long long k) {
+  if (k >= 0) (void)hipEventRecord(p->ev[2 * k + 1], p->stream);
+}
+
+int expected_nparams(int reaction, int S) {
+  switch (reaction) {
+    case RXN_LINEAR: return S;
+    case RXN_FHN: return 5;
+    case RXN_GRAY_SCOTT: return 2;
+    case RXN_SCHNAKENBERG: return 3;
+    case RXN_GM: return 5;
+    default: return -1;
+  }
+}
+
+// Transposed axis matrix Mt[j*n + k] = M[k][j] in FP64 (see kernels.h).
+std::vector<double> axis_matrix_t(int bc, long long n) {
+  const double pi = 3.14159265358979323846;
+  std::vector<double> Mt((size_t)n * n);
+  for (long long k = 0; k < n; ++k) {
+    for (long long j = 0; j < n; ++j) {
+      double v;
+      if (bc == SFRDE_BC_PERIODIC) {
+        const long long N = n;
+        const long long m = (k * j) % N;
+        const double th = 2.0 * pi * double(m) / double(N);
+        v = cos(th) + sin(th);
+      } else if (bc == SFRDE_BC_DIRICHLET) {
+        const long long N = n + 1;
+        const long long m = ((k + 1) * (j + 1)) % (2 * N);
+        v = sin(pi * double(m) / double(N));
+      } else {
+        const long long N = n - 1;
+        const long long m = (k * j) % (2 * N);
+        v = cos(pi * double(m) / double(N));
+        if (j == 0 || j == n - 1) v *= 0.5;
+      }
+      Mt[(size_t)j * n + k] = v;
+    }
+  }
+  return Mt;
+}
+
+double axis_inverse_scale(int bc, long long n) {
+  if (bc == SFRDE_BC_PERIODIC) return 1.0 / double(n);
+  if (bc == SFRDE_BC_DIRICHLET) return 2.0 / double(n + 1);
+  return 2.0 / double(n - 1);
+}
+
+long long pow2_floor(long long x) {
+  long long p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+
+void make_geom(sfrde_plan_s* p, int axis) {
+  Geom& g = p->geom[axis];
+  const long long n = p->n[axis];
+  long long inner = 1;
+  for (int a = 0; a < axis; ++a) inner *= p->n[a];
+  g.n = (int)n;
+  g.inner = inner;
+  g.total = p->total;
+  // Tile width: a power of two with n*W <= KMAX*NTHREADS, the tile of all
+  // species within 64 KB of LDS, and no wider than the lines available.
+  long long W = std::min<long long>(64, pow2_floor(std::max<long long>(1, (KMAX * NTHREADS) / n)));
+  while (W > 1 && (size_t)p->S * n * (W + 1) * p->w > 65536) W /= 2;
+  if (inner > 1) W = std::min<long long>(W, pow2_floor(inner) * (pow2_floor(inner) < inner ? 2 : 1));
+  g.W = (int)W;
+  g.pitch = (int)(W + 1);
+  if (inner == 1) {
+    g.outer = p->total / n;
+    g.tpo = 1;
+    g.ntiles = (g.outer + W - 1) / W;
+  } else {
+    g.outer = p->total / (n * inner);
+    g.tpo = (inner + W - 1) / W;
+    g.ntiles = g.outer * g.tpo;
+  }
+  size_t tile = (size_t)p->S * n * g.pitch * p->w;
+  p->lds[axis] = std::max<size_t>(tile, NTHREADS * sizeof(double));
+}
+
+// --------------------------------------------------------------------------
+template <typename T>
+StageArgs<T> stage_args(sfrde_plan_s* p, int axis, void* P) {
+  StageArgs<T> a{};
+  a.g = p->geom[axis];
+  a.Mt = (const T*)p->Mt[axis];
+  a.P = (T*)P;
+  a.coef = (const T*)p->coef;
+  a.dcoef = (const T*)p->dcoef;
+  a.uhat = (T*)p->uhat;
+  a.ctil = (T*)p->ctil;
+  a.acc = (T*)p->acc;
+  a.zh = (T*)p->zh;
+  a.aacc = (T*)p->aacc;
+  a.ahat = (T*)p->ahat;
+  a.gu = (T*)p->gu;
+  a.flag = p->flag;
+  a.rxn = p->rxn;
+  a.cs = T(p->cs);
+  a.S = p->S;
+  a.neumann = p->bc == SFRDE_BC_NEUMANN;
+  a.n0 = p->n[0];
+  a.n1 = p->n[1];
+  a.n2 = p->n[2];
+  return a;
+}
+
+template <typename T>
+int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre_div, int post_mul) {
+  SingleArgs<T> a{};
+  a.g = p->geom[axis];
+  a.Mt = (const T*)p->Mt[axis];
+  a.src = (const T*)src;
+  a.dst = (T*)dst;
+  a.S = p->S;
+  a.pre_divide_w = pre_div && p->bc == SFRDE_BC_NEUMANN;
+  a.post_multiply_w = post_mul && p->bc == SFRDE_BC_NEUMANN;
+  a.n0 = p->n[0];
+  a.n1 = p->n[1];
+  a.n2 = p->n[2];
+  const long long pk = prof_start(p, KC_Y);
+  hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[axis],
+                     p->stream, a);
+  prof_stop(p, pk);
+  HIPCHECK(hipGetLastError());
+  return SFRDE_OK;
+}
+
+// Stored data of one step inside the segment store.
+template <typename T>
+struct StepStore {
+  T* phys;  // [4][S][total]
+  T* uhat;  // [S][total]
+  T* fhat;  // [4][S][total]
+};
+
+template <typename T>
+StepStore<T> step_store(sfrde_plan_s* p, long long slot) {
+  StepStore<T> s{nullptr, nullptr, nullptr};
+  if (!p->seg) return s;
+  T* base = (T*)p->seg + (size_t)slot * 9 * p->S * p->total;
+  const size_t f = (size_t)p->S * p->total;
+  s.phys = base;
+  s.uhat = base + 4 * f;
+  s.fhat = base + 5 * f;
+  return s;
+}
+
+template <typename T>
+int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
+  StageArgs<T> a = stage_args<T>(p, 0, p->P);
+  a.mode = stage;
+  a.t = t;
+  a.st_phys = st_phys;
+  const long long pk = prof_start(p, KC_X);
+  hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
+                     p->stream, a);
+  prof_stop(p, pk);
+  HIPCHECK(hipGetLastError());
+  return SFRDE_OK;
+}
+
+template <typename T>
+int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat) {
+  const int ax = p->ndim - 1;
+  StageArgs<T> a = stage_args<T>(p, ax, p->P);
+  a.mode = mode;
+  a.src = (const T*)src;
+  a.st_uhat = st_uhat;
+  a.st_fhat = st_fhat;
+  const long long pk = prof_start(p, KC_Z);
+  hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
+                     p->stream, a);
+  prof_stop(p, pk);
+  HIPCHECK(hipGetLastError());
+  return SFRDE_OK;
+}
+
+// The middle axis of a 3D field (y), in place on buffer B.
+template <typename T>
+int ypass(sfrde_plan_s* p, void* B) {
+  if (p->ndim == 3) return launch_single<T>(p, 1, B, B, 0, 0);
+  return SFRDE_OK;
+}
+
+// u_hat = F u and P = the partial inverse of cs*u_hat that the first X
+// kernel expects (everything but the x axis).
+template <typename T>
+int prologue_physical(sfrde_plan_s* p, const void* state) {
+  TRY(launch_single<T>(p, 0, state, p->P, 0, 0));
+  TRY(ypass<T>(p, p->P));
+  TRY(launch_z<T>(p, MODE_INIT, nullptr, nullptr, nullptr));
+  return ypass<T>(p, p->P);
+}
+
+template <typename T>
+int prologue_spectral(sfrde_plan_s* p, const void* spec) {
+  HIPCHECK(hipMemcpyAsync(p->uhat, spec, field_bytes(p), hipMemcpyDeviceToDevice, p->stream));
+  TRY(launch_z<T>(p, MODE_RESTORE, p->uhat, nullptr, nullptr));
+  return ypass<T>(p, p->P);
+}
+
+// One step of eq. ETDRK4P13 from t (four stages); stores stage data if asked.
+template <typename T>
+int run_step(sfrde_plan_s* p, double t, const StepStore<T>* st) {
+  const double off[4] = {0.0, 0.5 * p->dt, 0.5 * p->dt, p->dt};
+  for (int j = 0; j < 4; ++j) {
+    TRY(launch_x<T>(p, j, t + off[j], st ? st->phys : nullptr));
+    TRY(ypass<T>(p, p->P));
+    TRY(launch_z<T>(p, j, nullptr, st ? st->uhat : nullptr, st ? st->fhat : nullptr));
+    TRY(ypass<T>(p, p->P));
+  }
+  return SFRDE_OK;
+}
+
+template <typename T>
+int fill(sfrde_plan_s* p, T* ptr, long long n, T v) {
+  if (n <= 0) return SFRDE_OK;
+  long long blocks = std::min<long long>((n + NTHREADS - 1) / NTHREADS, 65536);
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, ptr, n, v);
+  HIPCHECK(hipGetLastError());
+  return SFRDE_OK;
+}
+
+int write_header(sfrde_plan_s* p, void* ckpt, long long nsteps, long long K) {
+  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, p->stream, (long long*)ckpt, CKPT_MAGIC,
+                     nsteps, K, (long long)p->S, p->total, (long long)p->dtype,
+                     (long long)p->ndim, (long long)p->bc);
+  HIPCHECK(hipGetLastError());
+  return SFRDE_OK;
+}
+
+int check_header(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K) {
+  long long h[8];
+  HIPCHECK(hipMemcpyAsync(h, ckpt, sizeof(h), hipMemcpyDeviceToHost, p->stream));
+  HIPCHECK(hipStreamSynchronize(p->stream));
+  if (h[0] != CKPT_MAGIC) return fail(SFRDE_ESTATE, "checkpoint has no valid header");
+  if (h[3] != p->S || h[4] != p->total || h[5] != p->dtype || h[6] != p->ndim || h[7] != p->bc)
+    return fail(SFRDE_ESTATE, "checkpoint was written by a plan of another shape/dtype");
+  if (h[2] != K) return fail(SFRDE_ESTATE, "checkpoint spacing %lld != %lld", h[2], K);
+  if (h[1] < nsteps) return fail(SFRDE_ESTATE, "checkpoint covers %lld < %lld steps", h[1], nsteps);
+  return SFRDE_OK;
+}
+
+char* ckpt_slot(sfrde_plan_s* p, void* ckpt, long long slot) {
+  return (char*)ckpt + SFRDE_CKPT_HEADER_BYTES + (size_t)slot * field_bytes(p);
+}
+
+template <typename T>
+int finish_forward(sfrde_plan_s* p, void* state) {
+  TRY(launch_single<T>(p, 0, p->P, state, 0, 0));
+  HIPCHECK(hipMemcpyAsync(p->h_flag, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIPCHECK(hipStreamSynchronize(p->stream));
+  if (*p->h_flag) return fail(SFRDE_ENONFINITE, "a stage value or reaction became non-finite");
+  return SFRDE_OK;
+}
+
+template <typename T>
+int run_steps(sfrde_plan_s* p, long long k0, long long nsteps, double t0, long long K, void* ckpt) {
+  for (long long k = 0; k < nsteps; ++k) {
+    if (ckpt && K > 0 && k % K == 0)
+      HIPCHECK(hipMemcpyAsync(ckpt_slot(p, ckpt, k / K), p->uhat, field_bytes(p),
+                              hipMemcpyDeviceToDevice, p->stream));
+    TRY(run_step<T>(p, t0 + double(k0 + k) * p->dt, (const StepStore<T>*)nullptr));
+  }
+  return SFRDE_OK;
+}
+
+template <typename T>
+int integrate_t(sfrde_plan_s* p, void* state, long long nsteps, double t0, long long K, void* ckpt) {
+  TRY(fill<int>(p, p->flag, 1, 0));
+  if (ckpt && K > 0) TRY(write_header(p, ckpt, nsteps, K));
+  TRY(prologue_physical<T>(p, state));
+  TRY(run_steps<T>(p, 0, nsteps, t0, K, ckpt));
+  return finish_forward<T>(p, state);
+}
+
+template <typename T>
+int resume_t(sfrde_plan_s* p, const void* ckpt, long long slot, void* state, long long nsteps,
+             double t0, long long K, void* ckpt_out) {
+  TRY(fill<int>(p, p->flag, 1, 0));
+  if (ckpt_out && K > 0) TRY(write_header(p, ckpt_out, nsteps, K));
+  TRY(prologue_spectral<T>(p, ckpt_slot(p, (void*)ckpt, slot)));
+  TRY(run_steps<T>(p, 0, nsteps, t0, K, ckpt_out));
+  return finish_forward<T>(p, state);
+}
+
+// --------------------------------------------------------------------------
+template <typename T>
+int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
+  StageArgs<T> a = stage_args<T>(p, 0, p->Pa);
+  a.mode = stage;
+  a.st_phys = st.phys;
+  a.rp_acc = p->rp_acc;
+  const long long pk = prof_start(p, KC_XADJ);
+  hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
+                     p->stream, a);
+  prof_stop(p, pk);
+  HIPCHECK(hipGetLastError());
+  return SFRDE_OK;
+}
+
+template <typename T>
+int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
+  const int ax = p->ndim - 1;
+  StageArgs<T> a = stage_args<T>(p, ax, p->Pa);
+  a.mode = mode;
+  a.last = last;
+  a.G = p->G;
+  if (st) {
+    a.st_uhat = st->uhat;
+    a.st_fhat = st->fhat;
+  }
+  if (!p->G) a.dcoef = nullptr;
+  const long long pk = prof_start(p, KC_ZADJ);
+  hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
+                     p->stream, a);
+  prof_stop(p, pk);
+  HIPCHECK(hipGetLastError());
+  return SFRDE_OK;
+}
+
+// Reverse sweep over one step whose stage data sit in `st`.
+template <typename T>
+int adjoint_step(sfrde_plan_s* p, const StepStore<T>& st, int last) {
+  // adjoint stage m visits the forward stage value 3 - m (c, b, a, u)
+  for (int m = 0; m < 4; ++m) {
+    TRY(launch_xadj<T>(p, 3 - m, st));
+    TRY(ypass<T>(p, p->Pa));
+    TRY(launch_zadj<T>(p, m, &st, last));
+    TRY(ypass<T>(p, p->Pa));
+  }
+  return SFRDE_OK;
+}
+
+int ensure_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_theta, bool want_p) {
+  const size_t f = field_bytes(p);
+  TRY(dev_alloc(p, &p->Pa, f));
+  TRY(dev_alloc(p, &p->zh, f));
+  TRY(dev_alloc(p, &p->aacc, f));
+  TRY(dev_alloc(p, &p->ahat, f));
+  TRY(dev_alloc(p, &p->gu, f));
+  if (p->seg && p->seg_steps < seg_steps) dev_free(p, &p->seg, (size_t)p->seg_steps * 9 * f);
+  if (!p->seg) {
+    TRY(dev_alloc(p, &p->seg, (size_t)seg_steps * 9 * f));
+    p->seg_steps = seg_steps;
+  }
+  if (want_theta) {
+    TRY(dev_alloc(p, (void**)&p->G, (size_t)p->S * p->total * sizeof(double)));
+    if (!p->dcoef) {
+      TRY(dev_alloc(p, &p->dcoef, NCOEF * f));
+      CoefArgs c{};
+      c.lam0 = p->lam[0];
+      c.lam1 = p->lam[1];
+      c.lam2 = p->lam[2] ? p->lam[2] : p->lam[1];
+      c.n0 = p->n[0];
+      c.n1 = p->n[1];
+      c.n2 = p->n[2];
+      c.total = p->total;
+      c.S = p->S;
+      c.scheme = p->scheme;
+      c.deriv = 1;
+      c.tau = p->dt;
+      for (int s = 0; s < p->S; ++s) {
+        c.alpha[s] = p->alpha[s];
+        c.kappa[s] = p->kappa[s];
+      }
+      long long blocks = std::min<long long>((p->total + NTHREADS - 1) / NTHREADS, 8192);
+      if (p->dtype == SFRDE_F32)
+        hipLaunchKernelGGL(k_coefs<float>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
+                           (float*)p->dcoef);
+      else
+        hipLaunchKernelGGL(k_coefs<double>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream,
+                           c, (double*)p->dcoef);
+      HIPCHECK(hipGetLastError());
+    }
+  }
+  if (want_p) {
+    TRY(dev_alloc(p, (void**)&p->rp_acc,
+                  (size_t)MAX_PARAMS * p->geom[0].ntiles * sizeof(double)));
+  }
+  const long long need = 2 * MAX_SPECIES * 1024 + 64;
+  if (p->red && p->red_len < need) dev_free(p, (void**)&p->red, p->red_len * sizeof(double));
+  if (!p->red) {
+    TRY(dev_alloc(p, (void**)&p->red, need * sizeof(double)));
+    p->red_len = need;
+  }
+  return SFRDE_OK;
+}
+
+template <typename T>
+int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K, double t0,
+               const void* grad_uT, void* grad_u0, double* gk, double* ga, double* gp) {
+  const bool want_theta = gk || ga;
+  const bool want_p = gp != nullptr && p->rxn.np > 0;
+  const long long seg_steps = std::min(K, nsteps);
+  TRY(ensure_backward_buffers(p, seg_steps, want_theta, want_p));
+  // Buffers from an earlier call stay allocated; accumulate only what is asked.
+  double* G_saved = p->G;
+  if (!want_theta) p->G = nullptr;
+  if (p->G) TRY(fill<double>(p, p->G, (long long)p->S * p->total, 0.0));
+  double* rp_saved = p->rp_acc;
+  if (!want_p) p->rp_acc = nullptr;
+  if (p->rp_acc) TRY(fill<double>(p, p->rp_acc, (long long)MAX_PARAMS * p->geom[0].ntiles, 0.0));
+
+  int rc = SFRDE_OK;
+  do {
+    // cotangent of u(T) into the adjoint variables, then its first stage input
+    if ((rc = launch_single<T>(p, 0, grad_uT, p->Pa, 1, 0))) break;
+    if ((rc = ypass<T>(p, p->Pa))) break;
+    if ((rc = launch_zadj<T>(p, MODE_INIT, nullptr, 0))) break;
+    if ((rc = ypass<T>(p, p->Pa))) break;
+    const long long nseg = (nsteps + K - 1) / K;
+    for (long long sgi = nseg - 1; sgi >= 0 && rc == SFRDE_OK; --sgi) {
+      const long long k0 = sgi * K, k1 = std::min(nsteps, k0 + K);
+      if ((rc = prologue_spectral<T>(p, ckpt_slot(p, (void*)ckpt, sgi)))) break;
+      for (long long k = k0; k < k1 && rc == SFRDE_OK; ++k) {
+        StepStore<T> st = step_store<T>(p, k - k0);
+        rc = run_step<T>(p, t0 + double(k) * p->dt, &st);
+      }
+      for (long long k = k1 - 1; k >= k0 && rc == SFRDE_OK; --k) {
+        StepStore<T> st = step_store<T>(p, k - k0);
+        rc = adjoint_step<T>(p, st, k == 0);
+      }
+    }
+    if (rc) break;
+    if (grad_u0 && (rc = launch_single<T>(p, 0, p->Pa, grad_u0, 0, 1))) break;
+    const int nb = 1024;
+    double host[2 * MAX_SPECIES + MAX_PARAMS];
+    if (want_theta) {
+      CoefArgs c{};
+      c.lam0 = p->lam[0];
+      c.lam1 = p->lam[1];
+      c.lam2 = p->lam[2] ? p->lam[2] : p->lam[1];
+      c.n0 = p->n[0];
+      c.n1 = p->n[1];
+      c.n2 = p->n[2];
+      c.total = p->total;
+      c.S = p->S;
+      c.tau = p->dt;
+      for (int s = 0; s < p->S; ++s) {
+        c.alpha[s] = p->alpha[s];
+        c.kappa[s] = p->kappa[s];
+      }
+      hipLaunchKernelGGL(k_greduce, dim3(nb), dim3(NTHREADS), 0, p->stream, c, p->G, p->cs,
+                         (int)(p->bc == SFRDE_BC_NEUMANN), p->red);
+      if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_greduce launch"); break; }
+      hipLaunchKernelGGL(k_rowsum, dim3(2 * p->S), dim3(NTHREADS), 0, p->stream, p->red,
+                         (long long)nb, p->red + 2 * MAX_SPECIES * 1024);
+      if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
+      if (hipMemcpyAsync(host, p->red + 2 * MAX_SPECIES * 1024, 2 * p->S * sizeof(double),
+                         hipMemcpyDeviceToHost, p->stream) != hipSuccess) {
+        rc = fail(SFRDE_EDEVICE, "copy of gradient partials");
+        break;
+      }
+    }
+    if (want_p) {
+      hipLaunchKernelGGL(k_rowsum, dim3(p->rxn.np), dim3(NTHREADS), 0, p->stream, p->rp_acc,
+                         (long long)p->geom[0].ntiles, p->red + 2 * MAX_SPECIES * 1024 + 32);
+      if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
+      if (hipMemcpyAsync(host + 2 * MAX_SPECIES, p->red + 2 * MAX_SPECIES * 1024 + 32,
+                         p->rxn.np * sizeof(double), hipMemcpyDeviceToHost,
+                         p->stream) != hipSuccess) {
+        rc = fail(SFRDE_EDEVICE, "copy of parameter gradients");
+        break;
+      }
+    }
+    if (hipStreamSynchronize(p->stream) != hipSuccess) {
+      rc = fail(SFRDE_EDEVICE, "stream synchronize");
+      break;
+    }
+    for (int s = 0; s < p->S; ++s) {
+      if (gk) gk[s] = host[2 * s];
+      if (ga) ga[s] = host[2 * s + 1];
+    }
+    if (want_p)
+      for (int k = 0; k < p->rxn.np; ++k) gp[k] = host[2 * MAX_SPECIES + k];
+  } while (0);
+  p->G = G_saved;
+  p->rp_acc = rp_saved;
+  return rc;
+}
+
+void destroy_plan(sfrde_plan_s* p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->stream);
+  void** ptrs[] = {&p->Mt[0], &p->Mt[1], &p->Mt[2], (void**)&p->lam[0], (void**)&p->lam[1],
+                   (void**)&p->lam[2], &p->coef, &p->dcoef, &p->P, &p->uhat, &p->ctil, &p->acc,
+                   &p->Pa, &p->zh, &p->aacc, &p->ahat, &p->gu, (void**)&p->G, &p->seg,
+                   (void**)&p->rp_acc, (void**)&p->red, (void**)&p->flag};
+  for (void** q : ptrs) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  if (p->h_flag) (void)hipHostFree(p->h_flag);
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  delete p;
+}
+
+int validate(int32_t ndim, const int64_t* n, int32_t bc, const double* h, int32_t S,
+             const double* alpha, const double* kappa, double dt, int32_t reaction,
+             int32_t nparams, const double* params, int32_t dtype, int32_t scheme) {
+  if (ndim < 1 || ndim > 3) return fail(SFRDE_EINVAL, "ndim must be 1, 2 or 3 (got %d)", ndim);
+  if (!n || !h) return fail(SFRDE_EINVAL, "n and h must not be NULL");
+  for (int a = 0; a < ndim; ++a) {
+    if (n[a] < 2 || n[a] > MAX_N)
+      return fail(SFRDE_EINVAL, "n[%d] = %lld outside [2, %d]", a, (long long)n[a], MAX_N);
+    if (!(h[a] > 0.0) || !std::isfinite(h[a]))
+      return fail(SFRDE_EINVAL, "h[%d] must be finite and > 0", a);
+  }
+  if (bc < 0 || bc > 2) return fail(SFRDE_EINVAL, "unknown boundary condition %d", bc);
+  if (S < 1 || S > MAX_SPECIES) return fail(SFRDE_EINVAL, "nspecies %d outside [1, 4]", S);
+  if (!alpha || !kappa) return fail(SFRDE_EINVAL, "alpha and kappa must not be NULL");
+  for (int s = 0; s < S; ++s) {
+    if (!(alpha[s] > 0.0 && alpha[s] <= 2.0))
+      return fail(SFRDE_EINVAL, "alpha[%d] = %g outside (0, 2]", s, alpha[s]);
+    if (!(kappa[s] >= 0.0) || !std::isfinite(kappa[s]))
+      return fail(SFRDE_EINVAL, "kappa[%d] must be finite and >= 0", s);
+  }
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SFRDE_EINVAL, "dt must be finite and > 0");
+  if (reaction < 0 || reaction > 4) return fail(SFRDE_EINVAL, "unknown reaction %d", reaction);
+  if (reaction != RXN_LINEAR && S != 2)
+    return fail(SFRDE_EINVAL, "reaction %d needs exactly 2 species", reaction);
+  if (nparams != expected_nparams(reaction, S))
+    return fail(SFRDE_EINVAL, "reaction %d takes %d parameters (got %d)", reaction,
+                expected_nparams(reaction, S), nparams);
+  if (nparams > 0 && !params) return fail(SFRDE_EINVAL, "params must not be NULL");
+  for (int k = 0; k < nparams; ++k)
+    if (!std::isfinite(params[k])) return fail(SFRDE_EINVAL, "params[%d] is not finite", k);
+  if (dtype != SFRDE_F32 && dtype != SFRDE_F64) return fail(SFRDE_EINVAL, "unknown dtype %d", dtype);
+  if (scheme != SFRDE_SCHEME_P13 && scheme != SFRDE_SCHEME_EXP)
+    return fail(SFRDE_EINVAL, "unknown scheme %d", scheme);
+  if (ndim == 1) return fail(SFRDE_EUNSUPPORTED, "1D grids are not supported by this build");
+  return SFRDE_OK;
+}
+
+template <typename T>
+int upload_matrix(sfrde_plan_s* p, int axis) {
+  const long long n = p->n[axis];
+  std::vector<double> Mt = axis_matrix_t(p->bc, n);
+  std::vector<T> conv(Mt.size());
+  for (size_t i = 0; i < Mt.size(); ++i) conv[i] = T(Mt[i]);
+  TRY(dev_alloc(p, &p->Mt[axis], conv.size() * sizeof(T)));
+  HIPCHECK(hipMemcpy(p->Mt[axis], conv.data(), conv.size() * sizeof(T), hipMemcpyHostToDevice));
+  return SFRDE_OK;
+}
+
+int build_plan(sfrde_plan_s* p) {
+  for (int a = 0; a < p->ndim; ++a) {
+    if (p->dtype == SFRDE_F32)
+      TRY(upload_matrix<float>(p, a));
+    else
+      TRY(upload_matrix<double>(p, a));
+    std::vector<double> lam(p->n[a]);
+    for (long long k = 0; k < p->n[a]; ++k) lam[k] = axis_eigenvalue(p->bc, p->n[a], p->h[a], k);
+    TRY(dev_alloc(p, (void**)&p->lam[a], lam.size() * sizeof(double)));
+    HIPCHECK(hipMemcpy(p->lam[a], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  const size_t f = field_bytes(p);
+  TRY(dev_alloc(p, &p->coef, NCOEF * f));
+  TRY(dev_alloc(p, &p->P, f));
+  TRY(dev_alloc(p, &p->uhat, f));
+  TRY(dev_alloc(p, &p->ctil, f));
+  TRY(dev_alloc(p, &p->acc, f));
+  TRY(dev_alloc(p, (void**)&p->flag, 64));
+  HIPCHECK(hipHostMalloc((void**)&p->h_flag, sizeof(int), hipHostMallocDefault));
+  *p->h_flag = 0;
+  CoefArgs c{};
+  c.lam0 = p->lam[0];
+  c.lam1 = p->lam[1];
+  c.lam2 = p->lam[2] ? p->lam[2] : p->lam[1];
+  c.n0 = p->n[0];
+  c.n1 = p->n[1];
+  c.n2 = p->n[2];
+  c.total = p->total;
+  c.S = p->S;
+  c.scheme = p->scheme;
+  c.deriv = 0;
+  c.tau = p->dt;
+  for (int s = 0; s < p->S; ++s) {
+    c.alpha[s] = p->alpha[s];
+    c.kappa[s] = p->kappa[s];
+  }
+  long long blocks = std::min<long long>((p->total + NTHREADS - 1) / NTHREADS, 8192);
+  if (p->dtype == SFRDE_F32)
+    hipLaunchKernelGGL(k_coefs<float>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
+                       (float*)p->coef);
+  else
+    hipLaunchKernelGGL(k_coefs<double>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
+                       (double*)p->coef);
+  HIPCHECK(hipGetLastError());
+  TRY(fill<int>(p, p->flag, 16, 0));
+  HIPCHECK(hipStreamSynchronize(p->stream));
+  return SFRDE_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+extern "C" {
+
+const char* sfrde_last_error(void) { return g_err.c_str(); }
+
+int sfrde_plan(sfrde_plan_t* out, int32_t ndim, const int64_t* n, int32_t bc, const double* h,
+               int32_t nspecies, const double* alpha, const double* kappa, double dt,
+               int32_t reaction, int32_t nparams, const double* params, int32_t dtype,
+               int32_t scheme, void* hip_stream) {
+  g_err.clear();
+  if (!out) return fail(SFRDE_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  TRY(validate(ndim, n, bc, h, nspecies, alpha, kappa, dt, reaction, nparams, params, dtype,
+               scheme));
+  sfrde_plan_s* p = new (std::nothrow) sfrde_plan_s();
+  if (!p) return fail(SFRDE_ENOMEM, "host allocation of the plan failed");
+  p->ndim = ndim;
+  p->total = 1;
+  for (int a = 0; a < ndim; ++a) {
+    p->n[a] = n[a];
+    p->h[a] = h[a];
+    p->total *= n[a];
+    p->cs *= axis_inverse_scale(bc, n[a]);
+  }
+  p->bc = bc;
+  p->S = nspecies;
+  for (int s = 0; s < nspecies; ++s) {
+    p->alpha[s] = alpha[s];
+    p->kappa[s] = kappa[s];
+  }
+  p->dt = dt;
+  p->rxn.kind = reaction;
+  p->rxn.S = nspecies;
+  p->rxn.np = nparams;
+  for (int k = 0; k < nparams; ++k) p->rxn.p[k] = params[k];
+  p->dtype = dtype;
+  p->scheme = scheme;
+  p->stream = (hipStream_t)hip_stream;
+  p->w = dtype == SFRDE_F32 ? 4 : 8;
+  for (int a = 0; a < ndim; ++a) make_geom(p, a);
+  int rc = build_plan(p);
+  if (rc != SFRDE_OK) {
+    std::string msg = g_err;
+    destroy_plan(p);
+    g_err = msg;
+    return rc;
+  }
+  *out = p;
+  return SFRDE_OK;
+}
+
+int sfrde_destroy(sfrde_plan_t plan) {
+  g_err.clear();
+  if (!plan) return fail(SFRDE_EINVAL, "plan is NULL");
+  destroy_plan(plan);
+  return SFRDE_OK;
+}
+
+int sfrde_integrate(sfrde_plan_t p, void* state, int64_t nsteps, double t0, int64_t ckpt_every,
+                    void* ckpt) {
+  g_err.clear();
+  if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
+  if (!state) return fail(SFRDE_EINVAL, "state must not be NULL");
+  if (nsteps < 0) return fail(SFRDE_EINVAL, "nsteps must be >= 0");
+  if (ckpt_every < 0) return fail(SFRDE_EINVAL, "ckpt_every must be >= 0");
+  if (!std::isfinite(t0)) return fail(SFRDE_EINVAL, "t0 must be finite");
+  if (nsteps == 0) return SFRDE_OK;
+  if (p->dtype == SFRDE_F32) return integrate_t<float>(p, state, nsteps, t0, ckpt_every, ckpt);
+  return integrate_t<double>(p, state, nsteps, t0, ckpt_every, ckpt);
+}
+
+int sfrde_step(sfrde_plan_t p, void* state, double t) {
+  return sfrde_integrate(p, state, 1, t, 0, nullptr);
+}
+
+int64_t sfrde_ckpt_bytes(sfrde_plan_t p, int64_t nsteps, int64_t ckpt_every) {
+  g_err.clear();
+  if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
+  if (nsteps < 1 || ckpt_every < 1)
+    return fail(SFRDE_EINVAL, "nsteps and ckpt_every must be >= 1");
+  const int64_t nslots = (nsteps + ckpt_every - 1) / ckpt_every;
+  return SFRDE_CKPT_HEADER_BYTES + nslots * (int64_t)field_bytes(p);
+}
+
+int sfrde_resume(sfrde_plan_t p, const void* ckpt, int64_t slot, void* state, int64_t nsteps,
+                 double t0, int64_t ckpt_every, void* ckpt_out) {
+  g_err.clear();
+  if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
+  if (!ckpt || !state) return fail(SFRDE_EINVAL, "ckpt and state must not be NULL");
+  if (slot < 0 || nsteps < 0 || ckpt_every < 0) return fail(SFRDE_EINVAL, "negative argument");
+  long long h[8];
+  HIPCHECK(hipMemcpyAsync(h, ckpt, sizeof(h), hipMemcpyDeviceToHost, p->stream));
+  HIPCHECK(hipStreamSynchronize(p->stream));
+  if (h[0] != CKPT_MAGIC || h[3] != p->S || h[4] != p->total || h[5] != p->dtype)
+    return fail(SFRDE_ESTATE, "checkpoint does not match this plan");
+  const long long nslots = (h[1] + h[2] - 1) / h[2];
+  if (slot >= nslots) return fail(SFRDE_ESTATE, "slot %lld >= %lld slots", (long long)slot, nslots);
+  if (nsteps == 0) return SFRDE_OK;
+  if (p->dtype == SFRDE_F32)
+    return resume_t<float>(p, ckpt, slot, state, nsteps, t0, ckpt_every, ckpt_out);
+  return resume_t<double>(p, ckpt, slot, state, nsteps, t0, ckpt_every, ckpt_out);
+}
+
+int sfrde_backward(sfrde_plan_t p, const void* ckpt, int64_t nsteps, int64_t ckpt_every,
+                   double t0, const void* grad_uT, void* grad_u0, double* grad_kappa,
+                   double* grad_alpha, double* grad_params) {
+  g_err.clear();
+  if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
+  if (!ckpt || !grad_uT) return fail(SFRDE_EINVAL, "ckpt and grad_uT must not be NULL");
+  if (nsteps < 1 || ckpt_every < 1) return fail(SFRDE_EINVAL, "nsteps, ckpt_every must be >= 1");
+  TRY(check_header(p, ckpt, nsteps, ckpt_every));
+  if (p->dtype == SFRDE_F32)
+    return backward_t<float>(p, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0, grad_kappa,
+                             grad_alpha, grad_params);
+  return backward_t<double>(p, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0, grad_kappa,
+                            grad_alpha, grad_params);
+}
+
+int64_t sfrde_workspace_bytes(sfrde_plan_t p) {
+  if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
+  return (int64_t)p->bytes;
+}
+
+int sfrde_profile(sfrde_plan_t p, int32_t enable) {
+  g_err.clear();
+  if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
+  if (enable) {
+    HIPCHECK(hipStreamSynchronize(p->stream));
+    p->ev_used = 0;
+    // Pre-create events for `enable` launches so that recording does not
+    // create them inside a measured region.
+    while (p->ev.size() < 2 * (size_t)enable) {
+      hipEvent_t e;
+      HIPCHECK(hipEventCreate(&e));
+      p->ev.push_back(e);
+    }
+  }
+  p->prof = enable != 0;
+  return SFRDE_OK;
+}
+
+int sfrde_profile_read(sfrde_plan_t p, double* ms, int64_t* launches) {
+  g_err.clear();
+  if (!p || !ms || !launches) return fail(SFRDE_EINVAL, "NULL argument");
+  HIPCHECK(hipStreamSynchronize(p->stream));
+  for (int c = 0; c < KC_COUNT; ++c) {
+    ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (size_t k = 0; k < p->ev_used; ++k) {
+    float t = 0.f;
+    HIPCHECK(hipEventElapsedTime(&t, p->ev[2 * k], p->ev[2 * k + 1]));
+    ms[p->ev_class[k]] += double(t);
+    launches[p->ev_class[k]] += 1;
+  }
+  return SFRDE_OK;
+}
+
+int sfrde_axis_eigenvalues(int32_t bc, int64_t n, double h, double* out) {
+  g_err.clear();
+  if (bc < 0 || bc > 2 || n < 2 || !(h > 0) || !out) return fail(SFRDE_EINVAL, "bad argument");
+  for (int64_t k = 0; k < n; ++k) out[k] = axis_eigenvalue(bc, n, h, k);
+  return SFRDE_OK;
+}
+
+int sfrde_eval_coefficients(int32_t scheme, double L, double dt, int32_t deriv, double* out6) {
+  g_err.clear();
+  if ((scheme != 0 && scheme != 1) || !(L >= 0) || !(dt > 0) || !out6)
+    return fail(SFRDE_EINVAL, "bad argument");
+  if (deriv)
+    coef_derivs(scheme, L, dt, out6);
+  else
+    coef_values(scheme, L, dt, out6);
+  return SFRDE_OK;
+}
+
+}  // extern "C"

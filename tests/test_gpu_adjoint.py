@@ -1,0 +1,115 @@
+"""GPU adjoint (sfrde_backward through the C ABI) against the FP64 oracle's
+discrete adjoint, with segment recomputation from checkpoints."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import problem
+from paper_2003_13569_amd.torch_api import SFRDEFunction
+from tests.gpu_util import TD, plan_for
+from tests.test_gpu_parity import CASES
+
+pytestmark = pytest.mark.gpu
+
+M, K = 5, 2
+
+
+def _rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _gpu_grads(wl, u0, wbar, dtype, scheme=None):
+    p = plan_for(wl, dtype, scheme)
+    u = torch.tensor(u0, dtype=TD[dtype], device="cuda")
+    ckpt = p.integrate(u, M, 0.0, ckpt_every=K)
+    g_uT = torch.tensor(wbar, dtype=TD[dtype], device="cuda")
+    g_u0 = torch.empty_like(g_uT)
+    gk, ga, gp = p.backward(ckpt, M, K, g_uT, 0.0, g_u0)
+    torch.cuda.synchronize()
+    out = dict(uT=u.double().cpu().numpy(), u0=g_u0.double().cpu().numpy(), kappa=np.array(gk),
+               alpha=np.array(ga), params=np.array(gp))
+    p.close()
+    return out
+
+
+@pytest.mark.parametrize("scheme", ["p13", "exp"])
+@pytest.mark.parametrize("wl", CASES, ids=[c.name for c in CASES])
+def test_fp64_adjoint_matches_oracle(wl, scheme):
+    wl = wl.replace(scheme=scheme)
+    u0 = W.initial_fields(wl)
+    wbar = np.random.default_rng(11).standard_normal(u0.shape)
+    ref = problem.gradients(wl, u0, M, wbar)
+    got = _gpu_grads(wl, u0, wbar, "f64")
+    assert _rel(got["uT"], ref["uT"]) <= 1e-10
+    assert _rel(got["u0"], ref["u0"]) <= 1e-9
+    for key in ("kappa", "alpha", "params"):
+        r, g = ref[key], got[key]
+        scale = max(np.max(np.abs(r)), 1e-300)
+        assert np.max(np.abs(g - r)) <= 1e-9 * scale, (key, g, r)
+
+
+@pytest.mark.parametrize("wl", CASES[:4], ids=[c.name for c in CASES[:4]])
+def test_fp32_adjoint_matches_oracle(wl):
+    u0 = W.initial_fields(wl)
+    wbar = np.random.default_rng(12).standard_normal(u0.shape)
+    ref = problem.gradients(wl, u0, M, wbar)
+    got = _gpu_grads(wl, u0, wbar, "f32")
+    assert _rel(got["u0"], ref["u0"]) <= 1e-4
+    for key in ("kappa", "alpha", "params"):
+        r, g = ref[key], got[key]
+        assert np.max(np.abs(g - r)) <= 1e-3 * max(np.max(np.abs(r)), 1e-300), (key, g, r)
+
+
+def test_checkpoint_spacing_does_not_change_gradients():
+    wl = CASES[1]
+    u0 = W.initial_fields(wl)
+    wbar = np.random.default_rng(2).standard_normal(u0.shape)
+    outs = []
+    for k in (1, 2, 5):
+        p = plan_for(wl, "f64")
+        u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+        ckpt = p.integrate(u, M, 0.0, ckpt_every=k)
+        g0 = torch.empty_like(u)
+        gk, ga, gp = p.backward(ckpt, M, k, torch.tensor(wbar, device="cuda"), 0.0, g0)
+        outs.append((g0.cpu().numpy(), gk, ga, gp))
+        p.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert o[1] == outs[0][1] and o[2] == outs[0][2] and o[3] == outs[0][3]
+
+
+def test_autograd_function_gives_oracle_gradients():
+    wl = CASES[2]
+    u0 = W.initial_fields(wl)
+    wbar = np.random.default_rng(4).standard_normal(u0.shape)
+    ref = problem.gradients(wl, u0, M, wbar)
+    spec = dict(shape=wl.shape, bc=wl.bc, h=wl.h, dt=wl.dt, reaction=wl.reaction, nsteps=M,
+                ckpt_every=K, dtype="f64", scheme="p13")
+    x0 = torch.tensor(u0, dtype=torch.float64, device="cuda", requires_grad=True)
+    kap = torch.tensor(wl.kappa, dtype=torch.float64, requires_grad=True)
+    alp = torch.tensor(wl.alpha, dtype=torch.float64, requires_grad=True)
+    par = torch.tensor(wl.params, dtype=torch.float64, requires_grad=True)
+    uT = SFRDEFunction.apply(x0, kap, alp, par, spec)
+    loss = (uT * torch.tensor(wbar, device="cuda")).sum()
+    loss.backward()
+    assert _rel(x0.grad.cpu().numpy(), ref["u0"]) <= 1e-9
+    assert _rel(kap.grad.numpy(), ref["kappa"]) <= 1e-9
+    assert _rel(alp.grad.numpy(), ref["alpha"]) <= 1e-9
+    assert _rel(par.grad.numpy(), ref["params"]) <= 1e-9
+
+
+def test_incompatible_checkpoint_is_rejected():
+    from paper_2003_13569_amd import sfrde as C
+    wl = CASES[0]
+    p = plan_for(wl, "f64")
+    u = torch.tensor(W.initial_fields(wl), dtype=torch.float64, device="cuda")
+    ckpt = p.integrate(u, 4, 0.0, ckpt_every=2)
+    with pytest.raises(C.SfrdeError) as ei:
+        p.backward(ckpt, 4, 3, torch.zeros_like(u))
+    assert ei.value.code == C.ESTATE
+    with pytest.raises(C.SfrdeError) as ei:
+        p.backward(ckpt, 6, 2, torch.zeros_like(u))
+    assert ei.value.code == C.ESTATE
+    p.close()

@@ -1,0 +1,178 @@
+"""GPU parity: libsfrde (through the C ABI) against the FP64 oracle.
+
+FP64 results must agree with the oracle to 1e-10 and FP32 results to 2e-5
+(max over species of ||x - x_ref||_inf / ||x_ref||_inf) after the stated
+number of steps. Grids are small enough for the oracle but span several tiles
+with ragged tails.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import problem
+from paper_2003_13569_amd import sfrde as C
+from tests.gpu_util import TD, plan_for, run
+
+pytestmark = pytest.mark.gpu
+
+FHN = (0.1, 0.01, 0.5, 1.0, 0.0)
+GS = (0.04, 0.06)
+SCH = (1.0, 0.1305, 0.7695)
+GM = (0.1, 1.0, 1.0, 1.0, 1.0)
+
+
+def _wl(name, bc, shape, reaction, params, alpha, kappa, dt, init, domain, scheme="p13"):
+    return W.Workload(name=name, bc=bc, shape=shape, domain=domain, alpha=alpha, kappa=kappa,
+                      reaction=reaction, params=params, dt=dt, nsteps=5, seed=7, init=init,
+                      scheme=scheme)
+
+
+CASES = [
+    _wl("fhn2d-neu", "neumann", (37, 45), "fhn", FHN, (1.5, 1.5), (1e-2, 0.0), 0.1,
+        "fhn_noise", (0.0, 2.5)),
+    _wl("gs2d-per", "periodic", (40, 36), "gray_scott", GS, (1.7, 1.7), (2e-3, 1e-3), 1.0,
+        "gs_square", (-1.0, 1.0)),
+    _wl("gm2d-neu", "neumann", (33, 30), "gierer_meinhardt", GM, (1.6, 1.4), (1e-3, 0.05),
+        0.05, "gm_noise", (0.0, 2.0)),
+    _wl("sch2d-dir", "dirichlet", (31, 20), "schnakenberg", SCH, (1.8, 1.8), (0.05, 1.0), 0.01,
+        "schnak_noise", (0.0, 1.0)),
+    _wl("sch3d-dir", "dirichlet", (11, 13, 17), "schnakenberg", SCH, (1.8, 1.8), (0.05, 1.0),
+        0.01, "schnak_noise", (0.0, 1.0)),
+    _wl("sch3d-neu", "neumann", (9, 12, 10), "schnakenberg", SCH, (1.5, 1.2), (0.05, 1.0),
+        0.005, "schnak_noise", (0.0, 1.0)),
+    _wl("gs3d-per", "periodic", (8, 10, 12), "gray_scott", GS, (1.7, 1.9), (2e-3, 1e-3), 0.5,
+        "gs_square", (-1.0, 1.0)),
+]
+IDS = [c.name for c in CASES]
+
+
+@pytest.mark.parametrize("scheme", ["p13", "exp"])
+@pytest.mark.parametrize("wl", CASES, ids=IDS)
+def test_fp64_matches_oracle(wl, scheme):
+    wl = wl.replace(scheme=scheme)
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 5)
+    got = run(wl, u0, 5, "f64")
+    assert problem.rel_err(got, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("wl", CASES, ids=IDS)
+def test_fp32_matches_oracle(wl):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 5)
+    got = run(wl, u0, 5, "f32")
+    assert problem.rel_err(got, ref) <= 2e-5
+
+
+def test_linear_reaction_many_species():
+    wl = W.Workload(name="lin4", bc="dirichlet", shape=(14, 19), domain=(0.0, 1.0),
+                    alpha=(1.2, 1.5, 1.8, 2.0), kappa=(0.01, 0.02, 0.0, 0.05),
+                    reaction="linear", params=(0.3, -0.2, 1.0, 0.0), dt=0.02, nsteps=4, seed=3,
+                    init="normal", extra={"mean": [0.5, 0.4, 0.3, 0.2], "sd": 0.2})
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 4)
+    assert problem.rel_err(run(wl, u0, 4, "f64"), ref) <= 1e-10
+
+
+def test_config1_fhn_full_size_fp64():
+    # 2D FitzHugh-Nagumo, Neumann, 64x64, FP64, 100 steps of dt = 0.1.
+    wl = W.C1_FHN
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, wl.nsteps)
+    got = run(wl, u0, wl.nsteps, "f64")
+    assert problem.rel_err(got, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet", "neumann"])
+def test_minimum_grid_two_unknowns(bc):
+    wl = _wl("tiny", bc, (2, 3), "schnakenberg", SCH, (1.5, 1.5), (0.05, 1.0), 0.01,
+             "schnak_noise", (0.0, 1.0))
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 3)
+    assert problem.rel_err(run(wl, u0, 3, "f64"), ref) <= 1e-10
+
+
+def test_zero_steps_leave_state_untouched():
+    wl = CASES[0]
+    u0 = W.initial_fields(wl)
+    p = plan_for(wl, "f64")
+    u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    p.integrate(u, 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(u.cpu().numpy(), u0)
+    p.close()
+
+
+def test_runs_are_bitwise_deterministic():
+    wl = CASES[4]
+    u0 = W.initial_fields(wl)
+    a = run(wl, u0, 6, "f32")
+    b = run(wl, u0, 6, "f32")
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_resume_from_checkpoint_is_bitwise_identical(dtype):
+    wl = CASES[2]
+    u0 = W.initial_fields(wl)
+    p = plan_for(wl, dtype)
+    u = torch.tensor(u0, dtype=TD[dtype], device="cuda")
+    ckpt = p.integrate(u, 9, 0.0, ckpt_every=3)
+    v = torch.tensor(u0, dtype=TD[dtype], device="cuda")
+    p.resume(ckpt, 1, v, 6, t0=3 * wl.dt)
+    torch.cuda.synchronize()
+    assert torch.equal(u, v)
+    p.close()
+
+
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet", "neumann"])
+def test_single_eigenmode_decays_by_R13_power(bc):
+    # f = 0: M steps multiply an eigenmode by R13(L)^M (closed form).
+    ny, nx, tau, kappa, alpha, M = 10, 12, 0.02, 0.7, 1.3, 7
+
+    def mode(n, k):
+        jj = np.arange(n)
+        if bc == "periodic":
+            return np.cos(2 * np.pi * k * jj / n), np.sin(np.pi * k / n)
+        if bc == "dirichlet":
+            N = n + 1
+            return np.sin(np.pi * (jj + 1) * k / N), np.sin(np.pi * k / (2 * N))
+        N = n - 1
+        return np.cos(np.pi * jj * k / N), np.sin(np.pi * k / (2 * N))
+
+    wl = W.Workload(name="mode", bc=bc, shape=(ny, nx), domain=(0.0, 1.0), alpha=(alpha,),
+                    kappa=(kappa,), reaction="linear", params=(0.0,), dt=tau, nsteps=M, seed=0,
+                    init="normal")
+    hy, hx = wl.h
+    my, sy = mode(ny, 2)
+    mx, sx = mode(nx, 3)
+    lam = sum(4 * s * s / (hh * hh * (1 - s * s / 3)) for s, hh in ((sy, hy), (sx, hx)))
+    L = kappa * tau * lam ** (alpha / 2)
+    R = (24 - 6 * L) / (24 + 18 * L + 6 * L ** 2 + L ** 3)
+    u0 = np.outer(my, mx)[None]
+    p = plan_for(wl, "f64")
+    got = run(wl, u0, M, "f64", plan=p)
+    p.close()
+    assert np.max(np.abs(got - R ** M * u0)) <= 1e-12
+
+
+def test_nonfinite_reaction_is_reported():
+    wl = CASES[2]
+    u0 = W.initial_fields(wl)
+    u0[1, 5, 7] = 0.0  # Gierer-Meinhardt u^2/v at v = 0
+    p = plan_for(wl, "f64")
+    u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    with pytest.raises(C.SfrdeError) as ei:
+        p.integrate(u, 2)
+    assert ei.value.code == C.ENONFINITE
+    # the plan stays usable
+    u = torch.tensor(W.initial_fields(wl), dtype=torch.float64, device="cuda")
+    p.integrate(u, 1)
+    p.close()
+
+
+def test_null_state_is_rejected_on_a_live_plan():
+    p = plan_for(CASES[0], "f64")
+    assert C.lib().sfrde_integrate(p.handle, None, 1, 0.0, 0, None) == C.EINVAL
+    p.close()
