@@ -104,6 +104,141 @@ __device__ __forceinline__ void store_tile(const Geom& g, long long tile, const 
   }
 }
 
+// 16-byte vectors of the field type.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int N = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int N = 2;
+};
+template <typename T>
+__device__ __forceinline__ T vget(const typename Vec16<T>::type& v, int e);
+template <>
+__device__ __forceinline__ float vget<float>(const float4& v, int e) {
+  return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+}
+template <>
+__device__ __forceinline__ double vget<double>(const double2& v, int e) {
+  return e == 0 ? v.x : v.y;
+}
+template <typename T>
+__device__ __forceinline__ void vset(typename Vec16<T>::type& v, int e, T x);
+template <>
+__device__ __forceinline__ void vset<float>(float4& v, int e, float x) {
+  if (e == 0) v.x = x; else if (e == 1) v.y = x; else if (e == 2) v.z = x; else v.w = x;
+}
+template <>
+__device__ __forceinline__ void vset<double>(double2& v, int e, double x) {
+  if (e == 0) v.x = x; else v.y = x;
+}
+
+// Whether a tile can move in 16-byte vectors: full tile, vector-aligned rows.
+template <typename T>
+__device__ __forceinline__ bool tile_vectorizable(const Geom& g, long long tile, const void* p) {
+  constexpr int VW = Vec16<T>::N;
+  if (reinterpret_cast<unsigned long long>(p) & 15ull) return false;
+  if (g.total % VW) return false;
+  if (g.inner == 1) return (tile + 1) * g.W <= g.outer && (g.n % VW) == 0;
+  const long long o = tile / g.tpo;
+  return (tile - o * g.tpo + 1) * g.W <= g.inner && (g.inner % VW) == 0 && (g.W % VW) == 0;
+}
+
+// Vector index v of species s in a tile -> (global element, LDS row j, lane w).
+template <typename T>
+__device__ __forceinline__ void vec_coords(const Geom& g, long long tile, int v, long long& gidx,
+                                           int& j, int& w) {
+  constexpr int VW = Vec16<T>::N;
+  if (g.inner == 1) {
+    const int nv = g.n / VW;
+    w = v / nv;
+    j = (v - w * nv) * VW;  // first of VW consecutive rows
+    gidx = (tile * g.W + w) * (long long)g.n + j;
+  } else {
+    const int vpr = g.W / VW;
+    j = v / vpr;
+    w = (v - j * vpr) * VW;  // first of VW consecutive lanes
+    const long long o = tile / g.tpo;
+    const long long i0 = (tile - o * g.tpo) * g.W;
+    gidx = o * (long long)g.n * g.inner + (long long)j * g.inner + i0 + w;
+  }
+}
+
+// Tile load with every vector load of a thread issued before any use.
+template <typename T>
+__device__ __forceinline__ void load_tile_fast(const Geom& g, long long tile,
+                                               const T* __restrict__ src, T* buf, int S) {
+  if (!tile_vectorizable<T>(g, tile, src)) {
+    load_tile(g, tile, src, buf, S);
+    return;
+  }
+  using V = typename Vec16<T>::type;
+  constexpr int VW = Vec16<T>::N;
+  constexpr int CH = 4;
+  const int per_s = g.n * g.W / VW;
+  const int total_v = S * per_s;
+  for (int base = 0; base < total_v; base += CH * blockDim.x) {
+    V r[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int v = base + c * blockDim.x + threadIdx.x;
+      if (v < total_v) {
+        const int s = v / per_s;
+        long long gi;
+        int j, w;
+        vec_coords<T>(g, tile, v - s * per_s, gi, j, w);
+        r[c] = *reinterpret_cast<const V*>(src + s * g.total + gi);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int v = base + c * blockDim.x + threadIdx.x;
+      if (v < total_v) {
+        const int s = v / per_s;
+        long long gi;
+        int j, w;
+        vec_coords<T>(g, tile, v - s * per_s, gi, j, w);
+        T* b = buf + s * g.n * g.pitch;
+        for (int e = 0; e < VW; ++e) {
+          if (g.inner == 1)
+            b[(j + e) * g.pitch + w] = vget<T>(r[c], e);
+          else
+            b[j * g.pitch + w + e] = vget<T>(r[c], e);
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_tile_fast(const Geom& g, long long tile, const T* buf,
+                                                T* __restrict__ dst, int S) {
+  if (!tile_vectorizable<T>(g, tile, dst)) {
+    store_tile(g, tile, buf, dst, S);
+    return;
+  }
+  using V = typename Vec16<T>::type;
+  constexpr int VW = Vec16<T>::N;
+  const int per_s = g.n * g.W / VW;
+  const int total_v = S * per_s;
+  for (int v = threadIdx.x; v < total_v; v += blockDim.x) {
+    const int s = v / per_s;
+    long long gi;
+    int j, w;
+    vec_coords<T>(g, tile, v - s * per_s, gi, j, w);
+    const T* b = buf + s * g.n * g.pitch;
+    V r;
+    for (int e = 0; e < VW; ++e)
+      vset<T>(r, e, g.inner == 1 ? b[(j + e) * g.pitch + w] : b[j * g.pitch + w + e]);
+    *reinterpret_cast<V*>(dst + s * g.total + gi) = r;
+  }
+}
+
 // In-place dense transform of every species' tile: b[k][w] <- sum_j M[k][j] b[j][w].
 // Mt is the transposed matrix (Mt[j*n + k] = M[k][j]) so that the threads of
 // a wave read consecutive k.
@@ -184,17 +319,15 @@ struct StageArgs {
   long long n0, n1, n2;
 };
 
-// X kernel, forward: inverse-x, reaction, forward-x (in place on P).
+// ---------------------------------------------------------------- pointwise
+// Each phase walks the tile's elements in the coalescing order and works on
+// the LDS buffer buf[s][j][w] in place.
+
+// Forward reaction: buf holds the stage value (physical); replaced by f.
 template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_xstage(StageArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* buf = reinterpret_cast<T*>(smem_raw);
+__device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
-  const long long tile = blockIdx.x;
   const int S = a.S;
-  load_tile(g, tile, a.P, buf, S);
-  __syncthreads();
-  dense_transform(buf, S, g, a.Mt);
   bool bad = false;
   const int ne = g.n * g.W;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
@@ -213,26 +346,18 @@ __global__ __launch_bounds__(NTHREADS) void k_xstage(StageArgs<T> a) {
       buf[(s * g.n + j) * g.pitch + w] = f[s];
     }
   }
-  if (bad) a.flag[0] = 1;
-  __syncthreads();
-  dense_transform(buf, S, g, a.Mt);
-  store_tile(g, tile, buf, a.P, S);
+  return bad;
 }
 
-// Z kernel, forward: forward transform along the last axis, stage combine,
-// inverse transform (in place on P).
+// Forward stage combine: buf holds the transformed reaction (full spectral);
+// replaced by cs times the next stage's spectral value.
 template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* buf = reinterpret_cast<T*>(smem_raw);
+__device__ __forceinline__ void pw_combine(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
-  const long long tile = blockIdx.x;
   const int S = a.S;
-  load_tile(g, tile, a.src ? a.src : a.P, buf, S);
-  __syncthreads();
-  if (!a.src) dense_transform(buf, S, g, a.Mt);
   const int ne = g.n * g.W;
   const long long tot = g.total;
+  const long long cst = (long long)S * tot;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
     int j, w;
     unpack(g, e, j, w);
@@ -242,14 +367,13 @@ __global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
       T& cell = buf[(s * g.n + j) * g.pitch + w];
       const T fh = cell;
       const long long i = s * tot + idx;
-      const T* cf = a.coef + i;  // coefficient q at cf[q * S * tot]
-      const long long cst = (long long)S * tot;
+      const T* cf = a.coef + i;  // coefficient q at cf[q * cst]
       T out;
       switch (a.mode) {
         case 0: {
           const T uh = a.uhat[i];
           if (a.st_uhat) a.st_uhat[i] = uh;
-          if (a.st_fhat) a.st_fhat[0 * S * tot + i] = fh;
+          if (a.st_fhat) a.st_fhat[i] = fh;
           const T cQ = cf[C_Q * cst], cP = cf[C_PHI * cst];
           const T av = cQ * uh + cP * fh;
           a.ctil[i] = cQ * av - cP * fh;
@@ -258,21 +382,20 @@ __global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
           break;
         }
         case 1: {
-          if (a.st_fhat) a.st_fhat[1 * S * tot + i] = fh;
+          if (a.st_fhat) a.st_fhat[1 * cst + i] = fh;
           const T uh = a.uhat[i];
           out = cf[C_Q * cst] * uh + cf[C_PHI * cst] * fh;
           a.acc[i] += cf[C_PHI2 * cst] * fh;
           break;
         }
         case 2: {
-          if (a.st_fhat) a.st_fhat[2 * S * tot + i] = fh;
-          const T cP = cf[C_PHI * cst];
-          out = a.ctil[i] + T(2) * cP * fh;
+          if (a.st_fhat) a.st_fhat[2 * cst + i] = fh;
+          out = a.ctil[i] + T(2) * cf[C_PHI * cst] * fh;
           a.acc[i] += cf[C_PHI2 * cst] * fh;
           break;
         }
         case 3: {
-          if (a.st_fhat) a.st_fhat[3 * S * tot + i] = fh;
+          if (a.st_fhat) a.st_fhat[3 * cst + i] = fh;
           const T un = a.acc[i] + cf[C_PHI3 * cst] * fh;
           a.uhat[i] = un;
           out = un;
@@ -282,34 +405,109 @@ __global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
           a.uhat[i] = fh;
           out = fh;
           break;
-        default:  // MODE_RESTORE: src is the spectral state
+        default:  // MODE_RESTORE: the tile was loaded from the spectral state
           out = fh;
           break;
       }
       cell = a.cs * out;
     }
   }
-  __syncthreads();
-  dense_transform(buf, S, g, a.Mt);
-  store_tile(g, tile, buf, a.P, S);
 }
 
-// X kernel, adjoint: inverse-x of the spectral cotangent of f(stage value),
-// multiply by the transposed reaction Jacobian at the stored stage value,
-// forward-x. Accumulates the reaction-parameter gradient per block.
+// Vectorised forward combine for full tiles along a strided axis: each work
+// item is VW consecutive lanes of one row of one species, with all of its
+// global loads issued before the arithmetic. Falls back to pw_combine.
 template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* buf = reinterpret_cast<T*>(smem_raw);
+__device__ __forceinline__ void pw_combine_fast(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
-  const long long tile = blockIdx.x;
+  if (g.inner == 1 || a.mode > 3 || !tile_vectorizable<T>(g, tile, a.uhat)) {
+    pw_combine(a, buf, tile);
+    return;
+  }
+  using V = typename Vec16<T>::type;
+  constexpr int VW = Vec16<T>::N;
+  const int S = a.S;
+  const long long tot = g.total;
+  const long long cst = (long long)S * tot;
+  const int ngroups = g.n * g.W / VW;
+  const int mode = a.mode;
+  const T cs = a.cs;
+  for (int it = threadIdx.x; it < S * ngroups; it += blockDim.x) {
+    const int s = it / ngroups;
+    long long gi;
+    int j, w;
+    vec_coords<T>(g, tile, it - s * ngroups, gi, j, w);
+    const long long i = s * tot + gi;
+    const T* cf = a.coef + i;
+    T* cell = buf + (s * g.n + j) * g.pitch + w;
+    V fh, o0, o1, out;
+    for (int e = 0; e < VW; ++e) vset<T>(fh, e, cell[e]);
+    if (mode == 0) {
+      const V uh = *reinterpret_cast<const V*>(a.uhat + i);
+      const V cQ = *reinterpret_cast<const V*>(cf + C_Q * cst);
+      const V cP = *reinterpret_cast<const V*>(cf + C_PHI * cst);
+      const V cR = *reinterpret_cast<const V*>(cf + C_R * cst);
+      const V c1 = *reinterpret_cast<const V*>(cf + C_PHI1 * cst);
+      for (int e = 0; e < VW; ++e) {
+        const T f = vget<T>(fh, e), u = vget<T>(uh, e), q = vget<T>(cQ, e), p = vget<T>(cP, e);
+        const T av = q * u + p * f;
+        vset<T>(o0, e, q * av - p * f);
+        vset<T>(o1, e, vget<T>(cR, e) * u + vget<T>(c1, e) * f);
+        vset<T>(out, e, cs * av);
+      }
+      if (a.st_uhat) *reinterpret_cast<V*>(a.st_uhat + i) = uh;
+      if (a.st_fhat) *reinterpret_cast<V*>(a.st_fhat + i) = fh;
+      *reinterpret_cast<V*>(a.ctil + i) = o0;
+      *reinterpret_cast<V*>(a.acc + i) = o1;
+    } else if (mode == 1) {
+      const V uh = *reinterpret_cast<const V*>(a.uhat + i);
+      const V ac = *reinterpret_cast<const V*>(a.acc + i);
+      const V cQ = *reinterpret_cast<const V*>(cf + C_Q * cst);
+      const V cP = *reinterpret_cast<const V*>(cf + C_PHI * cst);
+      const V c2 = *reinterpret_cast<const V*>(cf + C_PHI2 * cst);
+      for (int e = 0; e < VW; ++e) {
+        const T f = vget<T>(fh, e);
+        vset<T>(out, e, cs * (vget<T>(cQ, e) * vget<T>(uh, e) + vget<T>(cP, e) * f));
+        vset<T>(o1, e, vget<T>(ac, e) + vget<T>(c2, e) * f);
+      }
+      if (a.st_fhat) *reinterpret_cast<V*>(a.st_fhat + cst + i) = fh;
+      *reinterpret_cast<V*>(a.acc + i) = o1;
+    } else if (mode == 2) {
+      const V ct = *reinterpret_cast<const V*>(a.ctil + i);
+      const V ac = *reinterpret_cast<const V*>(a.acc + i);
+      const V cP = *reinterpret_cast<const V*>(cf + C_PHI * cst);
+      const V c2 = *reinterpret_cast<const V*>(cf + C_PHI2 * cst);
+      for (int e = 0; e < VW; ++e) {
+        const T f = vget<T>(fh, e);
+        vset<T>(out, e, cs * (vget<T>(ct, e) + T(2) * vget<T>(cP, e) * f));
+        vset<T>(o1, e, vget<T>(ac, e) + vget<T>(c2, e) * f);
+      }
+      if (a.st_fhat) *reinterpret_cast<V*>(a.st_fhat + 2 * cst + i) = fh;
+      *reinterpret_cast<V*>(a.acc + i) = o1;
+    } else {
+      const V ac = *reinterpret_cast<const V*>(a.acc + i);
+      const V c3 = *reinterpret_cast<const V*>(cf + C_PHI3 * cst);
+      for (int e = 0; e < VW; ++e) {
+        const T un = vget<T>(ac, e) + vget<T>(c3, e) * vget<T>(fh, e);
+        vset<T>(o0, e, un);
+        vset<T>(out, e, cs * un);
+      }
+      if (a.st_fhat) *reinterpret_cast<V*>(a.st_fhat + 3 * cst + i) = fh;
+      *reinterpret_cast<V*>(a.uhat + i) = o0;
+    }
+    for (int e = 0; e < VW; ++e) cell[e] = vget<T>(out, e);
+  }
+}
+
+// Adjoint reaction: buf holds the cotangent of f(stage value) (physical);
+// replaced by J^T of it at the stored stage value. Reaction-parameter
+// partials are added to pacc (weighted by the Neumann point weights).
+template <typename T>
+__device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, long long tile,
+                                                double* pacc) {
+  const Geom& g = a.g;
   const int S = a.S;
   const bool want_p = a.rp_acc != nullptr;
-  load_tile(g, tile, a.P, buf, S);
-  __syncthreads();
-  dense_transform(buf, S, g, a.Mt);
-  double pacc[MAX_PARAMS];
-  for (int k = 0; k < MAX_PARAMS; ++k) pacc[k] = 0.0;
   const int ne = g.n * g.W;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
     int j, w;
@@ -325,31 +523,12 @@ __global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
     rxn_adjoint(a.rxn, u, gg, o, wgt, pacc, want_p);
     for (int s = 0; s < S; ++s) buf[(s * g.n + j) * g.pitch + w] = o[s];
   }
-  __syncthreads();
-  dense_transform(buf, S, g, a.Mt);
-  store_tile(g, tile, buf, a.P, S);
-  if (want_p) {
-    __syncthreads();
-    double* red = reinterpret_cast<double*>(smem_raw);
-    for (int k = 0; k < a.rxn.np; ++k) {
-      red[threadIdx.x] = pacc[k];
-      __syncthreads();
-      for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) a.rp_acc[(long long)k * gridDim.x + blockIdx.x] += red[0];
-      __syncthreads();
-    }
-  }
 }
 
-// Z kernel, adjoint: forward-z of J^T(...) (the cotangent of a stage's
-// spectral value), the adjoint combine, inverse-z. Cotangents are carried in
-// the variables for which the transposed transforms are the forward ones
-// (physical cotangents divided by the Neumann point weights, spectral ones
-// by the inverse scale and spectral weights). With z = cotangent of the
-// step output and X the incoming term of each stage:
+// Adjoint combine. Cotangents are carried in the variables for which the
+// transposed transforms are the forward ones (physical cotangents divided by
+// the Neumann point weights, spectral ones by the inverse scale and spectral
+// weights). With z = cotangent of the step output and X the incoming term:
 //   st 0 (c): aacc = R z; ahat = Q X; gu = phi1 z - phi X; out = phi2 z + 2 phi X
 //   st 1 (b): aacc += Q X; out = phi2 z + phi X
 //   st 2 (a): A = ahat + X; aacc += Q A; out = gu + phi A
@@ -357,15 +536,9 @@ __global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
 // G accumulates, per mode, y * g'(L) * x over every coefficient application
 // y_out = g(L) x of the forward step, for the kappa and alpha gradients.
 template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_zadj(StageArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* buf = reinterpret_cast<T*>(smem_raw);
+__device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
-  const long long tile = blockIdx.x;
   const int S = a.S;
-  load_tile(g, tile, a.P, buf, S);
-  __syncthreads();
-  dense_transform(buf, S, g, a.Mt);
   const int ne = g.n * g.W;
   const long long tot = g.total;
   const long long cst = (long long)S * tot;
@@ -435,9 +608,136 @@ __global__ __launch_bounds__(NTHREADS) void k_zadj(StageArgs<T> a) {
       cell = a.cs * out;
     }
   }
+}
+
+// Block-wide sum of pacc[0..np) added to rp_acc[k][blockIdx.x] (fixed order).
+__device__ __forceinline__ void block_add_partials(double* red, const double* pacc, int np,
+                                                   double* rp_acc) {
+  for (int k = 0; k < np; ++k) {
+    red[threadIdx.x] = pacc[k];
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) rp_acc[(long long)k * gridDim.x + blockIdx.x] += red[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- tile bodies
+// XF is the per-axis transform applied in place to every species' tile.
+template <bool FAST, typename T>
+__device__ __forceinline__ void tile_in(const Geom& g, long long tile, const T* src, T* buf, int S) {
+  if (FAST)
+    load_tile_fast(g, tile, src, buf, S);
+  else
+    load_tile(g, tile, src, buf, S);
+}
+
+template <bool FAST, typename T>
+__device__ __forceinline__ void tile_out(const Geom& g, long long tile, const T* buf, T* dst, int S) {
+  if (FAST)
+    store_tile_fast(g, tile, buf, dst, S);
+  else
+    store_tile(g, tile, buf, dst, S);
+}
+
+template <bool FAST, typename T, class XF>
+__device__ __forceinline__ void body_x(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
+  tile_in<FAST>(a.g, tile, a.P, buf, a.S);
   __syncthreads();
-  dense_transform(buf, S, g, a.Mt);
-  store_tile(g, tile, buf, a.P, S);
+  xf(buf, a.S);
+  const bool bad = pw_reaction(a, buf, tile);
+  if (bad) a.flag[0] = 1;
+  __syncthreads();
+  xf(buf, a.S);
+  tile_out<FAST>(a.g, tile, buf, a.P, a.S);
+}
+
+template <bool FAST, typename T, class XF>
+__device__ __forceinline__ void body_z(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
+  tile_in<FAST>(a.g, tile, a.src ? a.src : a.P, buf, a.S);
+  __syncthreads();
+  if (!a.src) xf(buf, a.S);
+  if (FAST)
+    pw_combine_fast(a, buf, tile);
+  else
+    pw_combine(a, buf, tile);
+  __syncthreads();
+  xf(buf, a.S);
+  tile_out<FAST>(a.g, tile, buf, a.P, a.S);
+}
+
+template <bool FAST, typename T, class XF>
+__device__ __forceinline__ void body_xadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf,
+                                          double* pacc) {
+  tile_in<FAST>(a.g, tile, a.P, buf, a.S);
+  __syncthreads();
+  xf(buf, a.S);
+  pw_adj_reaction(a, buf, tile, pacc);
+  __syncthreads();
+  xf(buf, a.S);
+  tile_out<FAST>(a.g, tile, buf, a.P, a.S);
+}
+
+template <bool FAST, typename T, class XF>
+__device__ __forceinline__ void body_zadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
+  tile_in<FAST>(a.g, tile, a.P, buf, a.S);
+  __syncthreads();
+  xf(buf, a.S);
+  pw_adj_combine(a, buf, tile);
+  __syncthreads();
+  xf(buf, a.S);
+  tile_out<FAST>(a.g, tile, buf, a.P, a.S);
+}
+
+// Dense transform as a functor (one tile per block).
+template <typename T>
+struct DenseXf {
+  const Geom* g;
+  const T* Mt;
+  __device__ __forceinline__ void operator()(T* buf, int S) { dense_transform(buf, S, *g, Mt); }
+};
+
+// X kernel, forward: inverse-x, reaction, forward-x (in place on P).
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_xstage(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  DenseXf<T> xf{&a.g, a.Mt};
+  body_x<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
+}
+
+// Z kernel, forward: forward transform along the last axis, stage combine,
+// inverse transform (in place on P).
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  DenseXf<T> xf{&a.g, a.Mt};
+  body_z<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
+}
+
+// X kernel, adjoint: inverse-x of the spectral cotangent of f(stage value),
+// transposed reaction Jacobian at the stored stage value, forward-x.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  DenseXf<T> xf{&a.g, a.Mt};
+  double pacc[MAX_PARAMS];
+  for (int k = 0; k < MAX_PARAMS; ++k) pacc[k] = 0.0;
+  body_xadj<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf, pacc);
+  if (a.rp_acc) {
+    __syncthreads();
+    block_add_partials(reinterpret_cast<double*>(smem_raw), pacc, a.rxn.np, a.rp_acc);
+  }
+}
+
+// Z kernel, adjoint: forward-z, adjoint combine, inverse-z.
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_zadj(StageArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  DenseXf<T> xf{&a.g, a.Mt};
+  body_zadj<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
 }
 
 // One transform along one axis, src -> dst (may alias), with optional

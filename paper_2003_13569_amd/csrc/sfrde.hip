@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -22,6 +23,7 @@
 #include "../../include/sfrde.h"
 #include "coef.h"
 #include "kernels.h"
+#include "mfma.h"
 
 using namespace sfrde;
 
@@ -76,6 +78,16 @@ struct sfrde_plan_s {
   size_t w = 4;   // bytes per real
   Geom geom[3]{};
   size_t lds[3] = {0, 0, 0};
+  // matrix-core variant per axis (see mfma.h)
+  bool use_m[3] = {false, false, false};
+  Geom geom_m[3]{};
+  size_t lds_m[3] = {0, 0, 0};
+  unsigned grid_m[3] = {0, 0, 0};
+  MfmaAxisDev mfax[3]{};
+  void* mf_A[3] = {nullptr, nullptr, nullptr};
+  void* mf_fold[3] = {nullptr, nullptr, nullptr};
+  void* mf_unfold[3] = {nullptr, nullptr, nullptr};
+  int n_cu = 256;
   // device memory
   void* Mt[3] = {nullptr, nullptr, nullptr};
   double* lam[3] = {nullptr, nullptr, nullptr};
@@ -232,11 +244,219 @@ void make_geom(sfrde_plan_s* p, int axis) {
   p->lds[axis] = std::max<size_t>(tile, NTHREADS * sizeof(double));
 }
 
+// ------------------------------------------------------------------ matrix cores
+// Folded form of one axis matrix (mfma.h): fold pairs, half matrices E and O,
+// the unfold of the result rows, and the fragment-ordered copies the waves
+// load into registers.
+struct MfmaTables {
+  bool ok = false;
+  int hK = 0, RBe = 0, RB = 0, ns = 0, rowsE = 0, rowsO = 0;
+  std::vector<unsigned> fold, unfold;
+  std::vector<double> E, O;  // [rows][hK]
+};
+
+double axis_entry(int bc, long long n, long long k, long long j) {
+  const double pi = 3.14159265358979323846;
+  if (bc == SFRDE_BC_DIRICHLET) {
+    const long long N = n + 1;
+    return sin(pi * double(((k + 1) * (j + 1)) % (2 * N)) / double(N));
+  }
+  const long long N = n - 1;  // Neumann
+  double v = cos(pi * double((k * j) % (2 * N)) / double(N));
+  if (j == 0 || j == n - 1) v *= 0.5;
+  return v;
+}
+
+MfmaTables mfma_tables(int bc, long long n) {
+  const double pi = 3.14159265358979323846;
+  MfmaTables t;
+  std::vector<std::pair<long long, long long>> pairs;  // (a, b), b = -1: fixed point
+  if (bc == SFRDE_BC_PERIODIC) {
+    const long long N = n;
+    pairs.push_back({0, -1});
+    for (long long j = 1; j < (N + 1) / 2; ++j) pairs.push_back({j, N - j});
+    if (N % 2 == 0) pairs.push_back({N / 2, -1});
+    t.rowsE = (int)(N / 2 + 1);
+    t.rowsO = t.rowsE;
+  } else {
+    for (long long j = 0; j < n / 2; ++j) pairs.push_back({j, n - 1 - j});
+    if (n % 2 == 1) pairs.push_back({(n - 1) / 2, -1});
+    t.rowsE = (int)((n + 1) / 2);
+    t.rowsO = (int)(n / 2);
+  }
+  t.ns = (int)pairs.size();
+  t.hK = ((t.ns + 31) / 32) * 32;
+  t.RBe = (t.rowsE + 15) / 16;
+  t.RB = t.RBe + (t.rowsO + 15) / 16;
+  t.ok = t.hK <= 128 && t.RB <= MF_WAVES;
+  if (!t.ok) return t;
+  t.fold.assign(t.hK, 0xFFFFFFFFu);
+  for (int i = 0; i < t.ns; ++i) {
+    const unsigned a = (unsigned)pairs[i].first;
+    const unsigned b = pairs[i].second < 0 ? 0xFFFFu : (unsigned)pairs[i].second;
+    t.fold[i] = a | (b << 16);
+  }
+  t.E.assign((size_t)t.rowsE * t.hK, 0.0);
+  t.O.assign((size_t)t.rowsO * t.hK, 0.0);
+  for (int i = 0; i < t.ns; ++i) {
+    const long long a = pairs[i].first;
+    const bool fixed = pairs[i].second < 0;
+    for (int m = 0; m < t.rowsE; ++m) {
+      double e, o;
+      if (bc == SFRDE_BC_PERIODIC) {
+        const double th = 2.0 * pi * double((m * a) % n) / double(n);
+        e = cos(th);
+        o = fixed ? 0.0 : sin(th);
+      } else {
+        e = axis_entry(bc, n, 2 * m, a);
+        o = (fixed || m >= t.rowsO) ? 0.0 : axis_entry(bc, n, 2 * m + 1, a);
+      }
+      t.E[(size_t)m * t.hK + i] = e;
+      if (m < t.rowsO) t.O[(size_t)m * t.hK + i] = o;
+    }
+  }
+  auto code = [](int c) -> unsigned { return c == 1 ? 1u : (c == -1 ? 2u : 0u); };
+  const unsigned obase = 16u * (unsigned)t.RBe;
+  t.unfold.assign(n, 0u);
+  for (long long k = 0; k < n; ++k) {
+    unsigned r1, r2 = 0;
+    int c1 = 1, c2 = 0;
+    if (bc == SFRDE_BC_PERIODIC) {
+      const long long N = n;
+      const long long kk = k <= N / 2 ? k : N - k;
+      r1 = (unsigned)kk;
+      r2 = obase + (unsigned)kk;
+      c2 = k <= N / 2 ? 1 : -1;
+    } else {
+      r1 = (k % 2 == 0) ? (unsigned)(k / 2) : obase + (unsigned)((k - 1) / 2);
+    }
+    t.unfold[k] = r1 | (r2 << 12) | (code(c1) << 24) | (code(c2) << 26);
+  }
+  return t;
+}
+
+// bf16 bits of x rounded to nearest even (x exactly representable in float
+// after the caller's rounding).
+unsigned short host_bf16(double x) {
+  float f = (float)x;
+  unsigned u;
+  memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+double host_bf16_value(unsigned short h) {
+  unsigned u = (unsigned)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+double half_entry(const MfmaTables& t, int rb, int row16, int k) {
+  const bool isE = rb < t.RBe;
+  const int row = 16 * (isE ? rb : rb - t.RBe) + row16;
+  const int rows = isE ? t.rowsE : t.rowsO;
+  if (row >= rows || k >= t.hK) return 0.0;
+  return isE ? t.E[(size_t)row * t.hK + k] : t.O[(size_t)row * t.hK + k];
+}
+
+int setup_mfma_axis(sfrde_plan_s* p, int axis) {
+  const char* env = getenv("SFRDE_TRANSFORM");
+  if (env && strcmp(env, "dense") == 0) return SFRDE_OK;
+  MfmaTables t = mfma_tables(p->bc, p->n[axis]);
+  if (!t.ok) return SFRDE_OK;
+  const int W = p->dtype == SFRDE_F32 ? MfmaXfF32::W : MfmaXfF64::W;
+  // geometry
+  Geom& g = p->geom_m[axis];
+  g = p->geom[axis];
+  g.W = W;
+  g.pitch = W + 1;
+  if (g.inner == 1) {
+    g.tpo = 1;
+    g.ntiles = (g.outer + W - 1) / W;
+  } else {
+    g.tpo = (g.inner + W - 1) / W;
+    g.ntiles = g.outer * g.tpo;
+  }
+  MfmaAxisDev& ax = p->mfax[axis];
+  ax.hK = t.hK;
+  ax.RBe = t.RBe;
+  ax.RB = t.RB;
+  ax.fb_pitch = t.hK + (p->dtype == SFRDE_F32 ? 8 : 2);
+  ax.r_pitch = W + 1;
+  ax.direct = p->bc != SFRDE_BC_PERIODIC;
+  size_t tile_bytes = (size_t)p->S * g.n * g.pitch * p->w;
+  tile_bytes = (tile_bytes + 15) / 16 * 16;
+  // fold area: FP32 plans keep three bf16 terms of s and d; FP64 plans s and d.
+  const size_t fold_bytes = p->dtype == SFRDE_F32 ? (size_t)3 * 2 * W * ax.fb_pitch * 2
+                                                   : (size_t)2 * W * ax.fb_pitch * 8;
+  const size_t res_bytes = (size_t)16 * t.RB * ax.r_pitch * p->w;
+  ax.fb_off = (int)tile_bytes;
+  size_t lds = tile_bytes + std::max(fold_bytes, res_bytes);
+  lds = std::max<size_t>(lds, (size_t)MF_THREADS * sizeof(double));
+  if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: keep the dense kernels
+  p->lds_m[axis] = lds;
+  p->grid_m[axis] = (unsigned)std::min<long long>(g.ntiles, (long long)p->n_cu);
+  // fragment-ordered split matrices
+  if (p->dtype == SFRDE_F32) {
+    std::vector<unsigned short> frag((size_t)MF_WAVES * MF_KSMAX_F32 * 3 * 64 * 8, 0);
+    for (int rb = 0; rb < t.RB; ++rb)
+      for (int ks = 0; ks < MF_KSMAX_F32; ++ks)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < 8; ++e) {
+            const double v = half_entry(t, rb, lane % 16, 32 * ks + 8 * (lane / 16) + e);
+            const unsigned short h0 = host_bf16(v);
+            const double r1 = v - host_bf16_value(h0);
+            const unsigned short h1 = host_bf16(r1);
+            const double r2 = r1 - host_bf16_value(h1);
+            const unsigned short h2 = host_bf16(r2);
+            const unsigned short hs[3] = {h0, h1, h2};
+            for (int tt = 0; tt < 3; ++tt)
+              frag[((((size_t)rb * MF_KSMAX_F32 + ks) * 3 + tt) * 64 + lane) * 8 + e] = hs[tt];
+          }
+    TRY(dev_alloc(p, &p->mf_A[axis], frag.size() * sizeof(unsigned short)));
+    HIPCHECK(hipMemcpy(p->mf_A[axis], frag.data(), frag.size() * sizeof(unsigned short),
+                       hipMemcpyHostToDevice));
+  } else {
+    std::vector<double> frag((size_t)MF_WAVES * MF_KSMAX_F64 * 64, 0.0);
+    for (int rb = 0; rb < t.RB; ++rb)
+      for (int ks = 0; ks < MF_KSMAX_F64; ++ks)
+        for (int lane = 0; lane < 64; ++lane)
+          frag[((size_t)rb * MF_KSMAX_F64 + ks) * 64 + lane] =
+              half_entry(t, rb, lane % 16, 4 * ks + lane / 16);
+    TRY(dev_alloc(p, &p->mf_A[axis], frag.size() * sizeof(double)));
+    HIPCHECK(hipMemcpy(p->mf_A[axis], frag.data(), frag.size() * sizeof(double),
+                       hipMemcpyHostToDevice));
+  }
+  TRY(dev_alloc(p, &p->mf_fold[axis], t.fold.size() * sizeof(unsigned)));
+  HIPCHECK(hipMemcpy(p->mf_fold[axis], t.fold.data(), t.fold.size() * sizeof(unsigned),
+                     hipMemcpyHostToDevice));
+  TRY(dev_alloc(p, &p->mf_unfold[axis], t.unfold.size() * sizeof(unsigned)));
+  HIPCHECK(hipMemcpy(p->mf_unfold[axis], t.unfold.data(), t.unfold.size() * sizeof(unsigned),
+                     hipMemcpyHostToDevice));
+  ax.Afrag = p->mf_A[axis];
+  ax.fold = (const unsigned*)p->mf_fold[axis];
+  ax.unfold = (const unsigned*)p->mf_unfold[axis];
+  p->use_m[axis] = true;
+  return SFRDE_OK;
+}
+
+template <typename T>
+int set_lds_attrs(size_t bytes) {
+  const void* fns[] = {reinterpret_cast<const void*>(&k_xstage_m<T>),
+                       reinterpret_cast<const void*>(&k_zstage_m<T>),
+                       reinterpret_cast<const void*>(&k_xadj_m<T>),
+                       reinterpret_cast<const void*>(&k_zadj_m<T>),
+                       reinterpret_cast<const void*>(&k_single_m<T>)};
+  for (const void* f : fns)
+    HIPCHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return SFRDE_OK;
+}
+
 // --------------------------------------------------------------------------
 template <typename T>
 StageArgs<T> stage_args(sfrde_plan_s* p, int axis, void* P) {
   StageArgs<T> a{};
-  a.g = p->geom[axis];
+  a.g = p->use_m[axis] ? p->geom_m[axis] : p->geom[axis];
   a.Mt = (const T*)p->Mt[axis];
   a.P = (T*)P;
   a.coef = (const T*)p->coef;
@@ -262,7 +482,7 @@ StageArgs<T> stage_args(sfrde_plan_s* p, int axis, void* P) {
 template <typename T>
 int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre_div, int post_mul) {
   SingleArgs<T> a{};
-  a.g = p->geom[axis];
+  a.g = p->use_m[axis] ? p->geom_m[axis] : p->geom[axis];
   a.Mt = (const T*)p->Mt[axis];
   a.src = (const T*)src;
   a.dst = (T*)dst;
@@ -273,8 +493,12 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
   a.n1 = p->n[1];
   a.n2 = p->n[2];
   const long long pk = prof_start(p, KC_Y);
-  hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[axis],
-                     p->stream, a);
+  if (p->use_m[axis])
+    hipLaunchKernelGGL(k_single_m<T>, dim3(p->grid_m[axis]), dim3(MF_THREADS), p->lds_m[axis],
+                       p->stream, a, p->mfax[axis]);
+  else
+    hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[axis],
+                       p->stream, a);
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
@@ -307,8 +531,12 @@ int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
   a.t = t;
   a.st_phys = st_phys;
   const long long pk = prof_start(p, KC_X);
-  hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
-                     p->stream, a);
+  if (p->use_m[0])
+    hipLaunchKernelGGL(k_xstage_m<T>, dim3(p->grid_m[0]), dim3(MF_THREADS),
+                       p->lds_m[0], p->stream, a, p->mfax[0]);
+  else
+    hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
+                       p->stream, a);
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
@@ -323,8 +551,12 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat)
   a.st_uhat = st_uhat;
   a.st_fhat = st_fhat;
   const long long pk = prof_start(p, KC_Z);
-  hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
-                     p->stream, a);
+  if (p->use_m[ax])
+    hipLaunchKernelGGL(k_zstage_m<T>, dim3(p->grid_m[ax]), dim3(MF_THREADS),
+                       p->lds_m[ax], p->stream, a, p->mfax[ax]);
+  else
+    hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
+                       p->stream, a);
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
@@ -447,8 +679,12 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
   a.st_phys = st.phys;
   a.rp_acc = p->rp_acc;
   const long long pk = prof_start(p, KC_XADJ);
-  hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
-                     p->stream, a);
+  if (p->use_m[0])
+    hipLaunchKernelGGL(k_xadj_m<T>, dim3(p->grid_m[0]), dim3(MF_THREADS),
+                       p->lds_m[0], p->stream, a, p->mfax[0]);
+  else
+    hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
+                       p->stream, a);
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
@@ -467,8 +703,12 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
   }
   if (!p->G) a.dcoef = nullptr;
   const long long pk = prof_start(p, KC_ZADJ);
-  hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
-                     p->stream, a);
+  if (p->use_m[ax])
+    hipLaunchKernelGGL(k_zadj_m<T>, dim3(p->grid_m[ax]), dim3(MF_THREADS),
+                       p->lds_m[ax], p->stream, a, p->mfax[ax]);
+  else
+    hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
+                       p->stream, a);
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
@@ -485,6 +725,11 @@ int adjoint_step(sfrde_plan_s* p, const StepStore<T>& st, int last) {
     TRY(ypass<T>(p, p->Pa));
   }
   return SFRDE_OK;
+}
+
+// Blocks of the adjoint X kernel (each owns one accumulator per parameter).
+long long rp_blocks(const sfrde_plan_s* p) {
+  return p->use_m[0] ? (long long)p->grid_m[0] : p->geom[0].ntiles;
 }
 
 int ensure_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_theta, bool want_p) {
@@ -530,8 +775,7 @@ int ensure_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_thet
     }
   }
   if (want_p) {
-    TRY(dev_alloc(p, (void**)&p->rp_acc,
-                  (size_t)MAX_PARAMS * p->geom[0].ntiles * sizeof(double)));
+    TRY(dev_alloc(p, (void**)&p->rp_acc, (size_t)MAX_PARAMS * rp_blocks(p) * sizeof(double)));
   }
   const long long need = 2 * MAX_SPECIES * 1024 + 64;
   if (p->red && p->red_len < need) dev_free(p, (void**)&p->red, p->red_len * sizeof(double));
@@ -555,7 +799,7 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
   if (p->G) TRY(fill<double>(p, p->G, (long long)p->S * p->total, 0.0));
   double* rp_saved = p->rp_acc;
   if (!want_p) p->rp_acc = nullptr;
-  if (p->rp_acc) TRY(fill<double>(p, p->rp_acc, (long long)MAX_PARAMS * p->geom[0].ntiles, 0.0));
+  if (p->rp_acc) TRY(fill<double>(p, p->rp_acc, (long long)MAX_PARAMS * rp_blocks(p), 0.0));
 
   int rc = SFRDE_OK;
   do {
@@ -610,7 +854,7 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
     }
     if (want_p) {
       hipLaunchKernelGGL(k_rowsum, dim3(p->rxn.np), dim3(NTHREADS), 0, p->stream, p->rp_acc,
-                         (long long)p->geom[0].ntiles, p->red + 2 * MAX_SPECIES * 1024 + 32);
+                         rp_blocks(p), p->red + 2 * MAX_SPECIES * 1024 + 32);
       if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
       if (hipMemcpyAsync(host + 2 * MAX_SPECIES, p->red + 2 * MAX_SPECIES * 1024 + 32,
                          p->rxn.np * sizeof(double), hipMemcpyDeviceToHost,
@@ -641,7 +885,9 @@ void destroy_plan(sfrde_plan_s* p) {
   void** ptrs[] = {&p->Mt[0], &p->Mt[1], &p->Mt[2], (void**)&p->lam[0], (void**)&p->lam[1],
                    (void**)&p->lam[2], &p->coef, &p->dcoef, &p->P, &p->uhat, &p->ctil, &p->acc,
                    &p->Pa, &p->zh, &p->aacc, &p->ahat, &p->gu, (void**)&p->G, &p->seg,
-                   (void**)&p->rp_acc, (void**)&p->red, (void**)&p->flag};
+                   (void**)&p->rp_acc, (void**)&p->red, (void**)&p->flag, &p->mf_A[0],
+                   &p->mf_A[1], &p->mf_A[2], &p->mf_fold[0], &p->mf_fold[1], &p->mf_fold[2],
+                   &p->mf_unfold[0], &p->mf_unfold[1], &p->mf_unfold[2]};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
@@ -700,6 +946,9 @@ int upload_matrix(sfrde_plan_s* p, int axis) {
 }
 
 int build_plan(sfrde_plan_s* p) {
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  HIPCHECK(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
   for (int a = 0; a < p->ndim; ++a) {
     if (p->dtype == SFRDE_F32)
       TRY(upload_matrix<float>(p, a));
@@ -709,6 +958,17 @@ int build_plan(sfrde_plan_s* p) {
     for (long long k = 0; k < p->n[a]; ++k) lam[k] = axis_eigenvalue(p->bc, p->n[a], p->h[a], k);
     TRY(dev_alloc(p, (void**)&p->lam[a], lam.size() * sizeof(double)));
     HIPCHECK(hipMemcpy(p->lam[a], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  size_t lds_max = 0;
+  for (int a = 0; a < p->ndim; ++a) {
+    TRY(setup_mfma_axis(p, a));
+    lds_max = std::max(lds_max, p->lds_m[a]);
+  }
+  if (lds_max > 0) {
+    if (p->dtype == SFRDE_F32)
+      TRY(set_lds_attrs<float>(lds_max));
+    else
+      TRY(set_lds_attrs<double>(lds_max));
   }
   const size_t f = field_bytes(p);
   TRY(dev_alloc(p, &p->coef, NCOEF * f));
