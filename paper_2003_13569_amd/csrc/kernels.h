@@ -37,9 +37,10 @@ constexpr int KMAX = 32;  // outputs per thread in the dense transform: n*W <= K
 
 struct Geom {
   int n;            // length of the transformed axis
-  int W;            // lines per tile
+  int W;            // lines per tile (a power of two)
   int pitch;        // LDS row pitch (>= W)
-  int pad_;
+  int wshift;       // log2(W)
+  float inv_n;      // 1/n, for the element -> (line, row) split of x-axis tiles
   long long inner;  // stride of the axis (1 for x)
   long long outer;  // lines (inner == 1) or outer blocks of n*inner
   long long tpo;    // tiles per outer block (inner > 1)
@@ -47,34 +48,65 @@ struct Geom {
   long long total;  // points per species
 };
 
-// Global index of element (j, w) of a tile; false for lanes past the edge.
-__device__ __forceinline__ bool elem(const Geom& g, long long tile, int j, int w, long long& idx) {
+// Where a tile sits in the field, computed once per tile: element (j, w) is
+// at base + j*rs + w*cs, and lanes w >= wvalid lie past the edge.
+struct TileRef {
+  long long base;
+  int wvalid;
+  int rs, cs;
+};
+
+__device__ __forceinline__ TileRef tile_ref(const Geom& g, long long tile) {
+  TileRef t;
   if (g.inner == 1) {
-    long long line = tile * g.W + w;
-    idx = line * g.n + j;
-    return line < g.outer;
+    const long long line0 = tile * g.W;
+    t.base = line0 * g.n;
+    const long long left = g.outer - line0;
+    t.wvalid = left < g.W ? (int)left : g.W;
+    t.rs = 1;
+    t.cs = g.n;
+  } else {
+    const long long o = tile / g.tpo;
+    const long long i0 = (tile - o * g.tpo) * g.W;
+    t.base = o * (long long)g.n * g.inner + i0;
+    const long long left = g.inner - i0;
+    t.wvalid = left < g.W ? (int)left : g.W;
+    t.rs = (int)g.inner;
+    t.cs = 1;
   }
-  long long o = tile / g.tpo;
-  long long i = (tile - o * g.tpo) * g.W + w;
-  idx = o * (long long)g.n * g.inner + (long long)j * g.inner + i;
-  return i < g.inner;
+  return t;
+}
+
+// Global index of element (j, w) of a tile; false for lanes past the edge.
+__device__ __forceinline__ bool elem(const Geom& g, const TileRef& t, int j, int w, long long& idx) {
+  idx = t.base + (long long)j * t.rs + (long long)w * t.cs;
+  return w < t.wvalid;
+}
+
+// floor(e / n) for 0 <= e < 2^24 from a float reciprocal and one correction.
+__device__ __forceinline__ int div_n(int e, int n, float inv_n) {
+  int q = (int)((float)e * inv_n);
+  if (q * n > e) --q;
+  if ((q + 1) * n <= e) ++q;
+  return q;
 }
 
 // Element e of the tile in coalescing order: consecutive threads touch
 // consecutive global addresses.
 __device__ __forceinline__ void unpack(const Geom& g, int e, int& j, int& w) {
   if (g.inner == 1) {
-    w = e / g.n;
+    w = div_n(e, g.n, g.inv_n);
     j = e - w * g.n;
   } else {
-    j = e / g.W;
-    w = e - j * g.W;
+    j = e >> g.wshift;
+    w = e & (g.W - 1);
   }
 }
 
 template <typename T>
 __device__ __forceinline__ void load_tile(const Geom& g, long long tile, const T* __restrict__ src,
                                           T* buf, int S) {
+  const TileRef tr = tile_ref(g, tile);
   const int ne = g.n * g.W;
   for (int s = 0; s < S; ++s) {
     const T* sp = src + (long long)s * g.total;
@@ -83,7 +115,7 @@ __device__ __forceinline__ void load_tile(const Geom& g, long long tile, const T
       int j, w;
       unpack(g, e, j, w);
       long long idx;
-      b[j * g.pitch + w] = elem(g, tile, j, w, idx) ? sp[idx] : T(0);
+      b[j * g.pitch + w] = elem(g, tr, j, w, idx) ? sp[idx] : T(0);
     }
   }
 }
@@ -91,6 +123,7 @@ __device__ __forceinline__ void load_tile(const Geom& g, long long tile, const T
 template <typename T>
 __device__ __forceinline__ void store_tile(const Geom& g, long long tile, const T* buf,
                                            T* __restrict__ dst, int S) {
+  const TileRef tr = tile_ref(g, tile);
   const int ne = g.n * g.W;
   for (int s = 0; s < S; ++s) {
     T* dp = dst + (long long)s * g.total;
@@ -99,7 +132,7 @@ __device__ __forceinline__ void store_tile(const Geom& g, long long tile, const 
       int j, w;
       unpack(g, e, j, w);
       long long idx;
-      if (elem(g, tile, j, w, idx)) dp[idx] = b[j * g.pitch + w];
+      if (elem(g, tr, j, w, idx)) dp[idx] = b[j * g.pitch + w];
     }
   }
 }
@@ -140,40 +173,32 @@ __device__ __forceinline__ void vset<double>(double2& v, int e, double x) {
 
 // Whether a tile can move in 16-byte vectors: full tile, vector-aligned rows.
 template <typename T>
-__device__ __forceinline__ bool tile_vectorizable(const Geom& g, long long tile, const void* p) {
+__device__ __forceinline__ bool tile_vectorizable(const Geom& g, const TileRef& t, const void* p) {
   constexpr int VW = Vec16<T>::N;
   if (reinterpret_cast<unsigned long long>(p) & 15ull) return false;
   if (g.total % VW) return false;
-  if (g.inner == 1) return (tile + 1) * g.W <= g.outer && (g.n % VW) == 0;
-  const long long o = tile / g.tpo;
-  return (tile - o * g.tpo + 1) * g.W <= g.inner && (g.inner % VW) == 0 && (g.W % VW) == 0;
+  if (t.wvalid != g.W) return false;
+  if (g.inner == 1) return (g.n % VW) == 0;
+  return (g.inner % VW) == 0 && (g.W % VW) == 0;
 }
 
-// Vector index v of species s in a tile -> (global element, LDS row j, lane w).
+// Vector v of one species' tile -> (global element, LDS row j, lane w): VW
+// consecutive rows of one line (x axis) or VW consecutive lanes of one row.
 template <typename T>
-__device__ __forceinline__ void vec_coords(const Geom& g, long long tile, int v, long long& gidx,
+__device__ __forceinline__ void vec_coords(const Geom& g, const TileRef& t, int v, long long& gidx,
                                            int& j, int& w) {
   constexpr int VW = Vec16<T>::N;
-  if (g.inner == 1) {
-    const int nv = g.n / VW;
-    w = v / nv;
-    j = (v - w * nv) * VW;  // first of VW consecutive rows
-    gidx = (tile * g.W + w) * (long long)g.n + j;
-  } else {
-    const int vpr = g.W / VW;
-    j = v / vpr;
-    w = (v - j * vpr) * VW;  // first of VW consecutive lanes
-    const long long o = tile / g.tpo;
-    const long long i0 = (tile - o * g.tpo) * g.W;
-    gidx = o * (long long)g.n * g.inner + (long long)j * g.inner + i0 + w;
-  }
+  const int e = v * VW;
+  unpack(g, e, j, w);
+  gidx = t.base + (long long)j * t.rs + (long long)w * t.cs;
 }
 
 // Tile load with every vector load of a thread issued before any use.
 template <typename T>
 __device__ __forceinline__ void load_tile_fast(const Geom& g, long long tile,
                                                const T* __restrict__ src, T* buf, int S) {
-  if (!tile_vectorizable<T>(g, tile, src)) {
+  const TileRef tr = tile_ref(g, tile);
+  if (!tile_vectorizable<T>(g, tr, src)) {
     load_tile(g, tile, src, buf, S);
     return;
   }
@@ -188,10 +213,10 @@ __device__ __forceinline__ void load_tile_fast(const Geom& g, long long tile,
     for (int c = 0; c < CH; ++c) {
       const int v = base + c * blockDim.x + threadIdx.x;
       if (v < total_v) {
-        const int s = v / per_s;
+        const int s = v >= per_s ? (v >= 2 * per_s ? (v >= 3 * per_s ? 3 : 2) : 1) : 0;
         long long gi;
         int j, w;
-        vec_coords<T>(g, tile, v - s * per_s, gi, j, w);
+        vec_coords<T>(g, tr, v - s * per_s, gi, j, w);
         r[c] = *reinterpret_cast<const V*>(src + s * g.total + gi);
       }
     }
@@ -199,10 +224,10 @@ __device__ __forceinline__ void load_tile_fast(const Geom& g, long long tile,
     for (int c = 0; c < CH; ++c) {
       const int v = base + c * blockDim.x + threadIdx.x;
       if (v < total_v) {
-        const int s = v / per_s;
+        const int s = v >= per_s ? (v >= 2 * per_s ? (v >= 3 * per_s ? 3 : 2) : 1) : 0;
         long long gi;
         int j, w;
-        vec_coords<T>(g, tile, v - s * per_s, gi, j, w);
+        vec_coords<T>(g, tr, v - s * per_s, gi, j, w);
         T* b = buf + s * g.n * g.pitch;
         for (int e = 0; e < VW; ++e) {
           if (g.inner == 1)
@@ -215,10 +240,77 @@ __device__ __forceinline__ void load_tile_fast(const Geom& g, long long tile,
   }
 }
 
+// Register prefetch of a whole tile (persistent kernels): issue() starts the
+// global loads of a tile, commit() writes them into LDS. Tiles that cannot
+// move in vectors, or need more than CH vectors per thread, are loaded by
+// commit() directly.
+template <typename T, int CH>
+struct TilePrefetch {
+  typename Vec16<T>::type r[CH > 0 ? CH : 1];
+  bool ok;
+
+  __device__ __forceinline__ void issue(const Geom& g, long long tile, const T* __restrict__ src,
+                                        int S) {
+    constexpr int VW = Vec16<T>::N;
+    using V = typename Vec16<T>::type;
+    ok = false;
+    if (CH == 0 || tile >= g.ntiles) return;
+    const TileRef tr = tile_ref(g, tile);
+    ok = tile_vectorizable<T>(g, tr, src) && S * g.n * g.W / VW <= CH * (int)blockDim.x;
+    if (!ok) return;
+    const int per_s = g.n * g.W / VW;
+    const int total_v = S * per_s;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int v = c * blockDim.x + threadIdx.x;
+      if (v < total_v) {
+        const int s = v >= per_s ? (v >= 2 * per_s ? (v >= 3 * per_s ? 3 : 2) : 1) : 0;
+        long long gi;
+        int j, w;
+        vec_coords<T>(g, tr, v - s * per_s, gi, j, w);
+        r[c] = *reinterpret_cast<const V*>(src + s * g.total + gi);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void commit(const Geom& g, long long tile, const T* src, T* buf,
+                                         int S) {
+    constexpr int VW = Vec16<T>::N;
+    if (!ok) {
+      if (CH > 0)
+        load_tile(g, tile, src, buf, S);
+      else
+        load_tile_fast(g, tile, src, buf, S);
+      return;
+    }
+    const TileRef tr = tile_ref(g, tile);
+    const int per_s = g.n * g.W / VW;
+    const int total_v = S * per_s;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int v = c * blockDim.x + threadIdx.x;
+      if (v < total_v) {
+        const int s = v >= per_s ? (v >= 2 * per_s ? (v >= 3 * per_s ? 3 : 2) : 1) : 0;
+        long long gi;
+        int j, w;
+        vec_coords<T>(g, tr, v - s * per_s, gi, j, w);
+        T* b = buf + s * g.n * g.pitch;
+        for (int e = 0; e < VW; ++e) {
+          if (g.inner == 1)
+            b[(j + e) * g.pitch + w] = vget<T>(r[c], e);
+          else
+            b[j * g.pitch + w + e] = vget<T>(r[c], e);
+        }
+      }
+    }
+  }
+};
+
 template <typename T>
 __device__ __forceinline__ void store_tile_fast(const Geom& g, long long tile, const T* buf,
                                                 T* __restrict__ dst, int S) {
-  if (!tile_vectorizable<T>(g, tile, dst)) {
+  const TileRef tr = tile_ref(g, tile);
+  if (!tile_vectorizable<T>(g, tr, dst)) {
     store_tile(g, tile, buf, dst, S);
     return;
   }
@@ -227,10 +319,10 @@ __device__ __forceinline__ void store_tile_fast(const Geom& g, long long tile, c
   const int per_s = g.n * g.W / VW;
   const int total_v = S * per_s;
   for (int v = threadIdx.x; v < total_v; v += blockDim.x) {
-    const int s = v / per_s;
+    const int s = v >= per_s ? (v >= 2 * per_s ? (v >= 3 * per_s ? 3 : 2) : 1) : 0;
     long long gi;
     int j, w;
-    vec_coords<T>(g, tile, v - s * per_s, gi, j, w);
+    vec_coords<T>(g, tr, v - s * per_s, gi, j, w);
     const T* b = buf + s * g.n * g.pitch;
     V r;
     for (int e = 0; e < VW; ++e)
@@ -324,26 +416,31 @@ struct StageArgs {
 // the LDS buffer buf[s][j][w] in place.
 
 // Forward reaction: buf holds the stage value (physical); replaced by f.
+// Walks the LDS tile row by row (lanes w fastest); the global index is only
+// formed when stage values are stored.
 template <typename T>
 __device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
+  const TileRef tr = tile_ref(g, tile);
+  const RxnT<T> rx(a.rxn);
   const int S = a.S;
+  const int sstride = g.n * g.pitch;
   bool bad = false;
-  const int ne = g.n * g.W;
+  const int ne = g.n << g.wshift;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-    int j, w;
-    unpack(g, e, j, w);
-    long long idx;
-    if (!elem(g, tile, j, w, idx)) continue;
+    const int j = e >> g.wshift, w = e & (g.W - 1);
+    if (w >= tr.wvalid) continue;
+    T* cell = buf + j * g.pitch + w;
     T u[MAX_SPECIES], f[MAX_SPECIES];
-    for (int s = 0; s < S; ++s) u[s] = buf[(s * g.n + j) * g.pitch + w];
+    for (int s = 0; s < S; ++s) u[s] = cell[s * sstride];
     if (a.st_phys) {
+      const long long idx = tr.base + (long long)j * tr.rs + (long long)w * tr.cs;
       for (int s = 0; s < S; ++s) a.st_phys[((long long)a.mode * S + s) * g.total + idx] = u[s];
     }
-    rxn_eval(a.rxn, u, f);
+    rxn_eval_t(rx, u, f);
     for (int s = 0; s < S; ++s) {
       bad |= !isfinite(u[s]) || !isfinite(f[s]);
-      buf[(s * g.n + j) * g.pitch + w] = f[s];
+      cell[s * sstride] = f[s];
     }
   }
   return bad;
@@ -354,6 +451,7 @@ __device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long 
 template <typename T>
 __device__ __forceinline__ void pw_combine(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
+  const TileRef tr = tile_ref(g, tile);
   const int S = a.S;
   const int ne = g.n * g.W;
   const long long tot = g.total;
@@ -362,7 +460,7 @@ __device__ __forceinline__ void pw_combine(const StageArgs<T>& a, T* buf, long l
     int j, w;
     unpack(g, e, j, w);
     long long idx;
-    if (!elem(g, tile, j, w, idx)) continue;
+    if (!elem(g, tr, j, w, idx)) continue;
     for (int s = 0; s < S; ++s) {
       T& cell = buf[(s * g.n + j) * g.pitch + w];
       const T fh = cell;
@@ -420,7 +518,8 @@ __device__ __forceinline__ void pw_combine(const StageArgs<T>& a, T* buf, long l
 template <typename T>
 __device__ __forceinline__ void pw_combine_fast(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
-  if (g.inner == 1 || a.mode > 3 || !tile_vectorizable<T>(g, tile, a.uhat)) {
+  const TileRef tr = tile_ref(g, tile);
+  if (g.inner == 1 || a.mode > 3 || !tile_vectorizable<T>(g, tr, a.uhat)) {
     pw_combine(a, buf, tile);
     return;
   }
@@ -433,10 +532,10 @@ __device__ __forceinline__ void pw_combine_fast(const StageArgs<T>& a, T* buf, l
   const int mode = a.mode;
   const T cs = a.cs;
   for (int it = threadIdx.x; it < S * ngroups; it += blockDim.x) {
-    const int s = it / ngroups;
+    const int s = it >= ngroups ? (it >= 2 * ngroups ? (it >= 3 * ngroups ? 3 : 2) : 1) : 0;
     long long gi;
     int j, w;
-    vec_coords<T>(g, tile, it - s * ngroups, gi, j, w);
+    vec_coords<T>(g, tr, it - s * ngroups, gi, j, w);
     const long long i = s * tot + gi;
     const T* cf = a.coef + i;
     T* cell = buf + (s * g.n + j) * g.pitch + w;
@@ -506,6 +605,7 @@ template <typename T>
 __device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, long long tile,
                                                 double* pacc) {
   const Geom& g = a.g;
+  const TileRef tr = tile_ref(g, tile);
   const int S = a.S;
   const bool want_p = a.rp_acc != nullptr;
   const int ne = g.n * g.W;
@@ -513,7 +613,7 @@ __device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, l
     int j, w;
     unpack(g, e, j, w);
     long long idx;
-    if (!elem(g, tile, j, w, idx)) continue;
+    if (!elem(g, tr, j, w, idx)) continue;
     T u[MAX_SPECIES], gg[MAX_SPECIES], o[MAX_SPECIES];
     for (int s = 0; s < S; ++s) {
       gg[s] = buf[(s * g.n + j) * g.pitch + w];
@@ -538,6 +638,7 @@ __device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, l
 template <typename T>
 __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
+  const TileRef tr = tile_ref(g, tile);
   const int S = a.S;
   const int ne = g.n * g.W;
   const long long tot = g.total;
@@ -546,7 +647,7 @@ __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, lo
     int j, w;
     unpack(g, e, j, w);
     long long idx;
-    if (!elem(g, tile, j, w, idx)) continue;
+    if (!elem(g, tr, j, w, idx)) continue;
     for (int s = 0; s < S; ++s) {
       T& cell = buf[(s * g.n + j) * g.pitch + w];
       const T X = cell;
@@ -692,6 +793,45 @@ __device__ __forceinline__ void body_zadj(const StageArgs<T>& a, T* buf, long lo
   tile_out<FAST>(a.g, tile, buf, a.P, a.S);
 }
 
+// Bodies for tiles already staged in LDS (persistent kernels load ahead).
+template <typename T, class XF>
+__device__ __forceinline__ void run_x(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
+  xf(buf, a.S);
+  const bool bad = pw_reaction(a, buf, tile);
+  if (bad) a.flag[0] = 1;
+  __syncthreads();
+  xf(buf, a.S);
+  store_tile_fast(a.g, tile, buf, a.P, a.S);
+}
+
+template <typename T, class XF>
+__device__ __forceinline__ void run_z(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
+  if (!a.src) xf(buf, a.S);
+  pw_combine_fast(a, buf, tile);
+  __syncthreads();
+  xf(buf, a.S);
+  store_tile_fast(a.g, tile, buf, a.P, a.S);
+}
+
+template <typename T, class XF>
+__device__ __forceinline__ void run_xadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf,
+                                         double* pacc) {
+  xf(buf, a.S);
+  pw_adj_reaction(a, buf, tile, pacc);
+  __syncthreads();
+  xf(buf, a.S);
+  store_tile_fast(a.g, tile, buf, a.P, a.S);
+}
+
+template <typename T, class XF>
+__device__ __forceinline__ void run_zadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
+  xf(buf, a.S);
+  pw_adj_combine(a, buf, tile);
+  __syncthreads();
+  xf(buf, a.S);
+  store_tile_fast(a.g, tile, buf, a.P, a.S);
+}
+
 // Dense transform as a functor (one tile per block).
 template <typename T>
 struct DenseXf {
@@ -761,6 +901,7 @@ __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
   T* buf = reinterpret_cast<T*>(smem_raw);
   const Geom& g = a.g;
   const long long tile = blockIdx.x;
+  const TileRef tr = tile_ref(g, tile);
   load_tile(g, tile, a.src, buf, a.S);
   __syncthreads();
   const int ne = g.n * g.W;
@@ -769,7 +910,7 @@ __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
       int j, w;
       unpack(g, e, j, w);
       long long idx;
-      if (!elem(g, tile, j, w, idx)) continue;
+      if (!elem(g, tr, j, w, idx)) continue;
       const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
       for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] /= wt;
     }
@@ -781,7 +922,7 @@ __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
       int j, w;
       unpack(g, e, j, w);
       long long idx;
-      if (!elem(g, tile, j, w, idx)) continue;
+      if (!elem(g, tr, j, w, idx)) continue;
       const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
       for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] *= wt;
     }

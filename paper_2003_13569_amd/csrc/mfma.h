@@ -34,8 +34,9 @@ constexpr int MF_KSMAX_F64 = 32;  // K <= 128 in steps of 4
 
 struct MfmaAxisDev {
   const void* Afrag;      // fragment-ordered half matrices
-  const unsigned* fold;   // [hK]: a | b << 16 (0xFFFF = none)
-  const unsigned* unfold; // [n]: r1 | r2 << 12 | c1 << 24 | c2 << 26 (code 1: +1, 2: -1)
+  int n;                  // axis length
+  int ns;                 // folded entries (pairs and fixed points)
+  int periodic;           // Hartley fold (else DCT-I / DST-I)
   int hK;                 // folded length (multiple of 32)
   int RBe;                // 16-row blocks of E
   int RB;                 // 16-row blocks of E and O (<= 16)
@@ -49,8 +50,21 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float unfold_code(unsigned c) {
-  return c == 1u ? 1.0f : (c == 2u ? -1.0f : 0.0f);
+// Fold entry i: s_i = x[a] + x[b], d_i = x[a] - x[b]; b < 0 for a fixed point
+// of the reflection (d_i = 0), a < 0 for padding (s_i = d_i = 0).
+//   DCT-I / DST-I: pairs (i, n-1-i) for 2i+1 < n; the middle index when n is odd.
+//   Hartley (N = n): 0 and N/2 are fixed; pairs (i, N-i) otherwise.
+__device__ __forceinline__ void fold_pair(const MfmaAxisDev& ax, int i, int& a, int& b) {
+  if (i >= ax.ns) {
+    a = -1;
+    b = -1;
+    return;
+  }
+  a = i;
+  if (!ax.periodic)
+    b = 2 * i + 1 < ax.n ? ax.n - 1 - i : -1;
+  else
+    b = (i == 0 || 2 * i == ax.n) ? -1 : ax.n - i;
 }
 
 // Fold every line of one species' tile into fb: s rows then d rows, each
@@ -64,12 +78,12 @@ __device__ __forceinline__ void mf_fold(const T* x, int pitch, const MfmaAxisDev
     T sv[8], dv[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const unsigned f = ax.fold[i0 + e];
-      const unsigned a = f & 0xFFFFu, b = f >> 16;
-      const T xa = a != 0xFFFFu ? x[a * pitch + col] : T(0);
-      const T xb = b != 0xFFFFu ? x[b * pitch + col] : T(0);
+      int a, b;
+      fold_pair(ax, i0 + e, a, b);
+      const T xa = a >= 0 ? x[a * pitch + col] : T(0);
+      const T xb = b >= 0 ? x[b * pitch + col] : T(0);
       sv[e] = xa + xb;
-      dv[e] = b != 0xFFFFu ? xa - xb : T(0);
+      dv[e] = b >= 0 ? xa - xb : T(0);
     }
     T* ps = fb + col * ax.fb_pitch + i0;
     T* pd = fb + (W + col) * ax.fb_pitch + i0;
@@ -81,18 +95,18 @@ __device__ __forceinline__ void mf_fold(const T* x, int pitch, const MfmaAxisDev
   }
 }
 
-// Unfold the result rows R[row][col] into the tile x[k][col].
+// Hartley unfold of the result rows R[row][col] into the tile x[k][col]:
+// y_k = E_k + O_k for k <= N/2, y_k = E_{N-k} - O_{N-k} above.
 template <typename T, int W>
 __device__ __forceinline__ void mf_unfold(const T* R, const MfmaAxisDev& ax, int n, T* x, int pitch) {
   const int ne = n * W;
+  const int obase = 16 * ax.RBe;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
     const int k = e / W, col = e - k * W;
-    const unsigned u = ax.unfold[k];
-    const unsigned r1 = u & 0xFFFu, r2 = (u >> 12) & 0xFFFu;
-    const T c1 = T(unfold_code((u >> 24) & 3u)), c2 = T(unfold_code((u >> 26) & 3u));
-    T v = c1 * R[r1 * ax.r_pitch + col];
-    if (c2 != T(0)) v += c2 * R[r2 * ax.r_pitch + col];
-    x[k * pitch + col] = v;
+    const bool low = 2 * k <= n;
+    const int kk = low ? k : n - k;
+    const T ev = R[kk * ax.r_pitch + col], ov = R[(obase + kk) * ax.r_pitch + col];
+    x[k * pitch + col] = low ? ev + ov : ev - ov;
   }
 }
 
@@ -122,12 +136,12 @@ __device__ __forceinline__ void mf_fold_split(const float* x, int pitch, const M
     unsigned short hs[3][4], hd[3][4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const unsigned f = ax.fold[i0 + e];
-      const unsigned a = f & 0xFFFFu, b = f >> 16;
-      const float xa = a != 0xFFFFu ? x[a * pitch + col] : 0.f;
-      const float xb = b != 0xFFFFu ? x[b * pitch + col] : 0.f;
+      int a, b;
+      fold_pair(ax, i0 + e, a, b);
+      const float xa = a >= 0 ? x[a * pitch + col] : 0.f;
+      const float xb = b >= 0 ? x[b * pitch + col] : 0.f;
       split_pair(xa + xb, hs[0][e], hs[1][e], hs[2][e]);
-      split_pair(b != 0xFFFFu ? xa - xb : 0.f, hd[0][e], hd[1][e], hd[2][e]);
+      split_pair(b >= 0 ? xa - xb : 0.f, hd[0][e], hd[1][e], hd[2][e]);
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
@@ -269,16 +283,30 @@ struct MfmaXfF64 {
           if (ks < KS) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks], bp[4 * ks], acc, 0, 0, 0);
         }
       }
-      __syncthreads();
-      if (wave < ax->RB) {
-        // f64 16x16x4 result layout: lane l, register r holds row 4r + l/16, column l%16
+      // f64 16x16x4 result layout: lane l, register r holds row 4r + l/16, column l%16
+      if (ax->direct) {
+        // DCT-I / DST-I: E row m is output 2m, O row m is output 2m + 1.
+        if (wave < ax->RB) {
+          const bool isO = wave >= ax->RBe;
+          const int mb = 16 * (isO ? wave - ax->RBe : wave) + lane / 16;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          fb[(16 * wave + 4 * r + lane / 16) * ax->r_pitch + lane % 16] = acc[r];
+          for (int r = 0; r < 4; ++r) {
+            const int k = 2 * (mb + 4 * r) + (isO ? 1 : 0);
+            if (k < n) x[k * pitch + lane % 16] = acc[r];
+          }
+        }
+        __syncthreads();
+      } else {
+        __syncthreads();
+        if (wave < ax->RB) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            fb[(16 * wave + 4 * r + lane / 16) * ax->r_pitch + lane % 16] = acc[r];
+        }
+        __syncthreads();
+        mf_unfold<double, W>(fb, *ax, n, x, pitch);
+        __syncthreads();
       }
-      __syncthreads();
-      mf_unfold<double, W>(fb, *ax, n, x, pitch);
-      __syncthreads();
     }
   }
 };
@@ -297,15 +325,31 @@ template <typename T>
 using MfmaXf = typename MfmaXfSel<T>::type;
 
 // ------------------------------------------------------------------ kernels
-// Persistent: block b handles tiles b, b + gridDim.x, ...
+// Persistent: block b handles tiles b, b + gridDim.x, ... The global loads of
+// the next tile are issued before the current tile is computed.
+// Prefetch depth (16-byte vectors per thread) where the registers allow it:
+// the FP32 forward, single-axis and adjoint-X kernels; 0 loads in place.
+template <typename T>
+struct MfPrefetch {
+  static constexpr int fwd = 0;
+};
+template <>
+struct MfPrefetch<float> {
+  static constexpr int fwd = 4;
+};
 
 template <typename T>
 __global__ __launch_bounds__(MF_THREADS) void k_xstage_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
+  TilePrefetch<T, MfPrefetch<T>::fwd> pf;
+  pf.issue(a.g, blockIdx.x, a.P, a.S);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    body_x<true>(a, buf, tile, xf);
+    pf.commit(a.g, tile, a.P, buf, a.S);
+    __syncthreads();
+    pf.issue(a.g, tile + gridDim.x, a.P, a.S);
+    run_x(a, buf, tile, xf);
     __syncthreads();
   }
 }
@@ -315,8 +359,14 @@ __global__ __launch_bounds__(MF_THREADS) void k_zstage_m(StageArgs<T> a, MfmaAxi
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
+  const T* src = a.src ? a.src : a.P;
+  TilePrefetch<T, MfPrefetch<T>::fwd> pf;
+  pf.issue(a.g, blockIdx.x, src, a.S);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    body_z<true>(a, buf, tile, xf);
+    pf.commit(a.g, tile, src, buf, a.S);
+    __syncthreads();
+    pf.issue(a.g, tile + gridDim.x, src, a.S);
+    run_z(a, buf, tile, xf);
     __syncthreads();
   }
 }
@@ -328,8 +378,13 @@ __global__ __launch_bounds__(MF_THREADS) void k_xadj_m(StageArgs<T> a, MfmaAxisD
   MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   double pacc[MAX_PARAMS];
   for (int k = 0; k < MAX_PARAMS; ++k) pacc[k] = 0.0;
+  TilePrefetch<T, MfPrefetch<T>::fwd> pf;
+  pf.issue(a.g, blockIdx.x, a.P, a.S);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    body_xadj<true>(a, buf, tile, xf, pacc);
+    pf.commit(a.g, tile, a.P, buf, a.S);
+    __syncthreads();
+    pf.issue(a.g, tile + gridDim.x, a.P, a.S);
+    run_xadj(a, buf, tile, xf, pacc);
     __syncthreads();
   }
   if (a.rp_acc) block_add_partials(reinterpret_cast<double*>(smem_raw), pacc, a.rxn.np, a.rp_acc);
@@ -340,8 +395,13 @@ __global__ __launch_bounds__(MF_THREADS) void k_zadj_m(StageArgs<T> a, MfmaAxisD
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
+  TilePrefetch<T, 0> pf;
+  pf.issue(a.g, blockIdx.x, a.P, a.S);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    body_zadj<true>(a, buf, tile, xf);
+    pf.commit(a.g, tile, a.P, buf, a.S);
+    __syncthreads();
+    pf.issue(a.g, tile + gridDim.x, a.P, a.S);
+    run_zadj(a, buf, tile, xf);
     __syncthreads();
   }
 }
@@ -355,15 +415,19 @@ __global__ __launch_bounds__(MF_THREADS) void k_single_m(SingleArgs<T> a, MfmaAx
   MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const Geom& g = a.g;
   const int ne = g.n * g.W;
+  TilePrefetch<T, MfPrefetch<T>::fwd> pf;
+  pf.issue(g, blockIdx.x, a.src, a.S);
   for (long long tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
-    load_tile_fast(g, tile, a.src, buf, a.S);
+    pf.commit(g, tile, a.src, buf, a.S);
     __syncthreads();
+    pf.issue(g, tile + gridDim.x, a.src, a.S);
+    const TileRef tr = tile_ref(g, tile);
     if (a.pre_divide_w) {
       for (int e = threadIdx.x; e < ne; e += blockDim.x) {
         int j, w;
         unpack(g, e, j, w);
         long long idx;
-        if (!elem(g, tile, j, w, idx)) continue;
+        if (!elem(g, tr, j, w, idx)) continue;
         const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
         for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] /= wt;
       }
@@ -375,7 +439,7 @@ __global__ __launch_bounds__(MF_THREADS) void k_single_m(SingleArgs<T> a, MfmaAx
         int j, w;
         unpack(g, e, j, w);
         long long idx;
-        if (!elem(g, tile, j, w, idx)) continue;
+        if (!elem(g, tr, j, w, idx)) continue;
         const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
         for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] *= wt;
       }

@@ -17,6 +17,53 @@ struct Rxn {
   double p[MAX_PARAMS];
 };
 
+// Reaction parameters converted to the field type once per kernel.
+template <typename T>
+struct RxnT {
+  int kind, S;
+  T p[5];
+  T lin[MAX_SPECIES];
+  __device__ __forceinline__ explicit RxnT(const Rxn& r) : kind(r.kind), S(r.S) {
+    for (int k = 0; k < 5; ++k) p[k] = k < r.np ? T(r.p[k]) : T(0);
+    for (int s = 0; s < MAX_SPECIES; ++s) lin[s] = s < r.np ? T(r.p[s]) : T(0);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void rxn_eval_t(const RxnT<T>& r, const T* u, T* f) {
+  switch (r.kind) {
+    case RXN_LINEAR:
+      for (int s = 0; s < r.S; ++s) f[s] = r.lin[s] * u[s];
+      break;
+    case RXN_FHN: {
+      const T x = u[0], v = u[1];
+      f[0] = x * (T(1) - x) * (x - r.p[0]) - v;
+      f[1] = r.p[1] * (r.p[2] * x - r.p[3] * v - r.p[4]);
+      break;
+    }
+    case RXN_GRAY_SCOTT: {
+      const T x = u[0], v = u[1];
+      const T xvv = x * v * v;
+      f[0] = -xvv + r.p[0] * (T(1) - x);
+      f[1] = xvv - (r.p[0] + r.p[1]) * v;
+      break;
+    }
+    case RXN_SCHNAKENBERG: {
+      const T x = u[0], v = u[1];
+      const T xxv = x * x * v;
+      f[0] = r.p[0] * (r.p[1] - x + xxv);
+      f[1] = r.p[0] * (r.p[2] - xxv);
+      break;
+    }
+    default: {
+      const T x = u[0], v = u[1];
+      f[0] = r.p[0] - r.p[1] * x + r.p[2] * x * x / v;
+      f[1] = r.p[3] * x * x - r.p[4] * v;
+      break;
+    }
+  }
+}
+
 // f = f(u); u and f hold S values.
 template <typename T>
 __device__ __forceinline__ void rxn_eval(const Rxn& r, const T* u, T* f) {

@@ -85,8 +85,6 @@ struct sfrde_plan_s {
   unsigned grid_m[3] = {0, 0, 0};
   MfmaAxisDev mfax[3]{};
   void* mf_A[3] = {nullptr, nullptr, nullptr};
-  void* mf_fold[3] = {nullptr, nullptr, nullptr};
-  void* mf_unfold[3] = {nullptr, nullptr, nullptr};
   int n_cu = 256;
   // device memory
   void* Mt[3] = {nullptr, nullptr, nullptr};
@@ -231,6 +229,9 @@ void make_geom(sfrde_plan_s* p, int axis) {
   if (inner > 1) W = std::min<long long>(W, pow2_floor(inner) * (pow2_floor(inner) < inner ? 2 : 1));
   g.W = (int)W;
   g.pitch = (int)(W + 1);
+  g.wshift = 0;
+  while ((1 << g.wshift) < g.W) ++g.wshift;
+  g.inv_n = 1.0f / (float)n;
   if (inner == 1) {
     g.outer = p->total / n;
     g.tpo = 1;
@@ -245,13 +246,12 @@ void make_geom(sfrde_plan_s* p, int axis) {
 }
 
 // ------------------------------------------------------------------ matrix cores
-// Folded form of one axis matrix (mfma.h): fold pairs, half matrices E and O,
-// the unfold of the result rows, and the fragment-ordered copies the waves
-// load into registers.
+// Folded form of one axis matrix (mfma.h): the half matrices E and O over the
+// fold pairs (the same pairs fold_pair() computes on the device), from which
+// the fragment-ordered copies the waves load into registers are made.
 struct MfmaTables {
   bool ok = false;
   int hK = 0, RBe = 0, RB = 0, ns = 0, rowsE = 0, rowsO = 0;
-  std::vector<unsigned> fold, unfold;
   std::vector<double> E, O;  // [rows][hK]
 };
 
@@ -290,12 +290,6 @@ MfmaTables mfma_tables(int bc, long long n) {
   t.RB = t.RBe + (t.rowsO + 15) / 16;
   t.ok = t.hK <= 128 && t.RB <= MF_WAVES;
   if (!t.ok) return t;
-  t.fold.assign(t.hK, 0xFFFFFFFFu);
-  for (int i = 0; i < t.ns; ++i) {
-    const unsigned a = (unsigned)pairs[i].first;
-    const unsigned b = pairs[i].second < 0 ? 0xFFFFu : (unsigned)pairs[i].second;
-    t.fold[i] = a | (b << 16);
-  }
   t.E.assign((size_t)t.rowsE * t.hK, 0.0);
   t.O.assign((size_t)t.rowsO * t.hK, 0.0);
   for (int i = 0; i < t.ns; ++i) {
@@ -314,23 +308,6 @@ MfmaTables mfma_tables(int bc, long long n) {
       t.E[(size_t)m * t.hK + i] = e;
       if (m < t.rowsO) t.O[(size_t)m * t.hK + i] = o;
     }
-  }
-  auto code = [](int c) -> unsigned { return c == 1 ? 1u : (c == -1 ? 2u : 0u); };
-  const unsigned obase = 16u * (unsigned)t.RBe;
-  t.unfold.assign(n, 0u);
-  for (long long k = 0; k < n; ++k) {
-    unsigned r1, r2 = 0;
-    int c1 = 1, c2 = 0;
-    if (bc == SFRDE_BC_PERIODIC) {
-      const long long N = n;
-      const long long kk = k <= N / 2 ? k : N - k;
-      r1 = (unsigned)kk;
-      r2 = obase + (unsigned)kk;
-      c2 = k <= N / 2 ? 1 : -1;
-    } else {
-      r1 = (k % 2 == 0) ? (unsigned)(k / 2) : obase + (unsigned)((k - 1) / 2);
-    }
-    t.unfold[k] = r1 | (r2 << 12) | (code(c1) << 24) | (code(c2) << 26);
   }
   return t;
 }
@@ -370,6 +347,8 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   g = p->geom[axis];
   g.W = W;
   g.pitch = W + 1;
+  g.wshift = 0;
+  while ((1 << g.wshift) < g.W) ++g.wshift;
   if (g.inner == 1) {
     g.tpo = 1;
     g.ntiles = (g.outer + W - 1) / W;
@@ -427,15 +406,10 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
     HIPCHECK(hipMemcpy(p->mf_A[axis], frag.data(), frag.size() * sizeof(double),
                        hipMemcpyHostToDevice));
   }
-  TRY(dev_alloc(p, &p->mf_fold[axis], t.fold.size() * sizeof(unsigned)));
-  HIPCHECK(hipMemcpy(p->mf_fold[axis], t.fold.data(), t.fold.size() * sizeof(unsigned),
-                     hipMemcpyHostToDevice));
-  TRY(dev_alloc(p, &p->mf_unfold[axis], t.unfold.size() * sizeof(unsigned)));
-  HIPCHECK(hipMemcpy(p->mf_unfold[axis], t.unfold.data(), t.unfold.size() * sizeof(unsigned),
-                     hipMemcpyHostToDevice));
   ax.Afrag = p->mf_A[axis];
-  ax.fold = (const unsigned*)p->mf_fold[axis];
-  ax.unfold = (const unsigned*)p->mf_unfold[axis];
+  ax.n = (int)p->n[axis];
+  ax.ns = t.ns;
+  ax.periodic = p->bc == SFRDE_BC_PERIODIC;
   p->use_m[axis] = true;
   return SFRDE_OK;
 }
@@ -886,8 +860,7 @@ void destroy_plan(sfrde_plan_s* p) {
                    (void**)&p->lam[2], &p->coef, &p->dcoef, &p->P, &p->uhat, &p->ctil, &p->acc,
                    &p->Pa, &p->zh, &p->aacc, &p->ahat, &p->gu, (void**)&p->G, &p->seg,
                    (void**)&p->rp_acc, (void**)&p->red, (void**)&p->flag, &p->mf_A[0],
-                   &p->mf_A[1], &p->mf_A[2], &p->mf_fold[0], &p->mf_fold[1], &p->mf_fold[2],
-                   &p->mf_unfold[0], &p->mf_unfold[1], &p->mf_unfold[2]};
+                   &p->mf_A[1], &p->mf_A[2]};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
