@@ -14,10 +14,9 @@
 // W lines the block folds the data in LDS, each wave runs its row block over
 // all lines, results go back to LDS and are unfolded into the tile.
 //
-// FP32 fields: products on v_mfma_f32_16x16x32_bf16 with both operands split
-// into three bf16 terms (x = x0 + x1 + x2, each the rounding of what is left)
-// and the six products with term orders summing to at most 2, accumulated in
-// FP32 from the smallest terms up: about the accuracy of an FP32 product.
+// FP32 fields: products on v_mfma_f32_16x16x32_f16 with both operands split
+// into two binary16 terms after a per-column power-of-two scaling, three
+// products accumulated in FP32: about the accuracy of an FP32 product.
 // FP64 fields: v_mfma_f64_16x16x4_f64 on the unsplit values.
 #pragma once
 
@@ -46,7 +45,6 @@ struct MfmaAxisDev {
   int direct;             // unfold is the even/odd row interleave (DCT-I, DST-I)
 };
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
@@ -111,129 +109,197 @@ __device__ __forceinline__ void mf_unfold(const T* R, const MfmaAxisDev& ax, int
 }
 
 // ------------------------------------------------------------------ FP32
-// Fold buffer: three bf16 terms of s and d, [term][half][col][fb_pitch]
-// (bf16 bits), written once per element by the fold.
-__device__ __forceinline__ void split_pair(float x, unsigned short& h0, unsigned short& h1,
-                                           unsigned short& h2) {
-  const __bf16 a = (__bf16)x;
-  const float r1 = x - (float)a;
-  const __bf16 b = (__bf16)r1;
-  const float r2 = r1 - (float)b;
-  const __bf16 c = (__bf16)r2;
-  h0 = __builtin_bit_cast(unsigned short, a);
-  h1 = __builtin_bit_cast(unsigned short, b);
-  h2 = __builtin_bit_cast(unsigned short, c);
+// Products on v_mfma_f32_16x16x32_f16. Both operands are split into two
+// binary16 terms, v = v0 + v1 with v0 the rounding of v and v1 the rounding
+// of what is left, and the three products A0 X0 + A0 X1 + A1 X0 are
+// accumulated in FP32 (the dropped A1 X1 is below 2^-22 of the column
+// scale). The matrices hold bounded entries (|a| <= sqrt 2); each folded data
+// column is scaled by a power of two that puts its largest magnitude in
+// [2^14, 2^15), so neither term leaves the binary16 range, and the results
+// are scaled back exactly.
+//
+// Fold buffer (LDS, binary16 bits): [term][half s|d][col][F32_FBP], then the
+// W inverse column scales as floats. F32_FBP = 136 leaves room for folded
+// lengths up to 128 and keeps the 16-byte accesses free of bank conflicts.
+constexpr int F32_FBP = 136;
+constexpr int f32_fold_bytes(int W) { return 2 * 2 * W * F32_FBP * 2 + W * 4; }
+
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+
+// Two scaled floats -> packed binary16 head and tail terms.
+__device__ __forceinline__ void split2_f16(float x0, float x1, float sc, unsigned& t0,
+                                           unsigned& t1) {
+  const f2v x = {x0 * sc, x1 * sc};
+  const h2v a = __builtin_convertvector(x, h2v);
+  const f2v r = x - __builtin_convertvector(a, f2v);
+  const h2v b = __builtin_convertvector(r, h2v);
+  t0 = __builtin_bit_cast(unsigned, a);
+  t1 = __builtin_bit_cast(unsigned, b);
 }
 
-template <int W>
-__device__ __forceinline__ void mf_fold_split(const float* x, int pitch, const MfmaAxisDev& ax,
-                                              unsigned short* fb) {
-  const int items = W * (ax.hK / 4);
-  const int tstride = 2 * W * ax.fb_pitch;  // elements between terms
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int col = it % W;
-    const int i0 = (it / W) * 4;
-    unsigned short hs[3][4], hd[3][4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      int a, b;
-      fold_pair(ax, i0 + e, a, b);
-      const float xa = a >= 0 ? x[a * pitch + col] : 0.f;
-      const float xb = b >= 0 ? x[b * pitch + col] : 0.f;
-      split_pair(xa + xb, hs[0][e], hs[1][e], hs[2][e]);
-      split_pair(b >= 0 ? xa - xb : 0.f, hd[0][e], hd[1][e], hd[2][e]);
-    }
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      const uint2 vs = make_uint2(hs[t][0] | ((unsigned)hs[t][1] << 16),
-                                  hs[t][2] | ((unsigned)hs[t][3] << 16));
-      const uint2 vd = make_uint2(hd[t][0] | ((unsigned)hd[t][1] << 16),
-                                  hd[t][2] | ((unsigned)hd[t][3] << 16));
-      *reinterpret_cast<uint2*>(fb + t * tstride + col * ax.fb_pitch + i0) = vs;
-      *reinterpret_cast<uint2*>(fb + t * tstride + (W + col) * ax.fb_pitch + i0) = vd;
-    }
-  }
+// Maximum over the 16 lanes of a DPP row (lanes 16r .. 16r+15).
+__device__ __forceinline__ float row16_max(float m) {
+  m = fmaxf(m, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                             0, __builtin_bit_cast(int, m), 0x128, 0xf, 0xf, false)));
+  m = fmaxf(m, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                             0, __builtin_bit_cast(int, m), 0x124, 0xf, 0xf, false)));
+  m = fmaxf(m, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                             0, __builtin_bit_cast(int, m), 0x122, 0xf, 0xf, false)));
+  m = fmaxf(m, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+                                             0, __builtin_bit_cast(int, m), 0x121, 0xf, 0xf, false)));
+  return m;
 }
 
 struct MfmaXfF32 {
   static constexpr int W = 32;
-  const Geom* g;
+  static constexpr int P = W + 1;             // LDS row pitch of the tile
+  static constexpr int FBP = F32_FBP;
+  static constexpr int TS = 2 * W * F32_FBP;  // binary16 elements between the two terms
+  static constexpr int FOLD_THREADS = 16 * W; // one 16-lane row per column
   const MfmaAxisDev* ax;
   unsigned short* fb;
-  bf16x8 A[MF_KSMAX_F32][3];
-  int wave, lane;
+  float* scl;  // inverse column scales
+  f16x8 A[MF_KSMAX_F32][2];
+  int n, KS;
+  bool mf;     // this wave owns a row block
+  bool direct;
+  int bofs;    // this lane's B-fragment offset in fb
+  // fold work item of this thread: column col, entries i0 .. i0+7
+  bool ffast;
+  int i0, col, fa, fbb;
+  // output rows of this lane's results (direct unfold)
+  int xrow, rmask;
 
-  __device__ __forceinline__ MfmaXfF32(const Geom* g_, const MfmaAxisDev* ax_, float* fb_)
-      : g(g_), ax(ax_), fb(reinterpret_cast<unsigned short*>(fb_)) {
-    wave = threadIdx.x / 64;
-    lane = threadIdx.x % 64;
+  __device__ __forceinline__ MfmaXfF32(const Geom*, const MfmaAxisDev* ax_, float* fb_)
+      : ax(ax_), fb(reinterpret_cast<unsigned short*>(fb_)) {
+    scl = reinterpret_cast<float*>(fb + 2 * TS);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    n = ax->n;
+    KS = ax->hK >> 5;
+    mf = wave < ax->RB;
+    direct = ax->direct != 0;
     const uint4* src = reinterpret_cast<const uint4*>(ax->Afrag);
 #pragma unroll
     for (int ks = 0; ks < MF_KSMAX_F32; ++ks)
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
+      for (int t = 0; t < 2; ++t) {
         uint4 v = make_uint4(0, 0, 0, 0);
-        if (wave < ax->RB) v = src[((wave * MF_KSMAX_F32 + ks) * 3 + t) * 64 + lane];
-        A[ks][t] = __builtin_bit_cast(bf16x8, v);
+        if (mf) v = src[((wave * MF_KSMAX_F32 + ks) * 2 + t) * 64 + lane];
+        A[ks][t] = __builtin_bit_cast(f16x8, v);
       }
+    const bool isO = wave >= ax->RBe;
+    bofs = ((isO ? W : 0) + lane % 16) * FBP + 8 * (lane / 16);
+    // fold item; entries past the folded length come out as zeros
+    col = (threadIdx.x >> 4) & (W - 1);
+    i0 = (threadIdx.x & 15) << 3;
+    const int bstart = ax->periodic ? n : n - 1;  // partner of entry i is bstart - i
+    ffast = ax->periodic ? (i0 >= 1 && 2 * (i0 + 7) < n) : (2 * (i0 + 7) + 1 < n);
+    fa = i0 * P + col;
+    fbb = (bstart - i0) * P + col;
+    // direct unfold: E row m -> output 2m, O row m -> output 2m + 1
+    const int mb = 16 * (isO ? wave - ax->RBe : wave) + 4 * (lane / 16);
+    const int row0 = 2 * mb + (isO ? 1 : 0);
+    xrow = row0 * P + lane % 16;
+    rmask = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (mf && row0 + 2 * r < n) rmask |= 1 << r;
+  }
+
+  __device__ __forceinline__ void fold(const float* x) {
+    if ((int)threadIdx.x >= FOLD_THREADS) return;
+    float sv[8], dv[8];
+    if (ffast) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float xa = x[fa + e * P], xb = x[fbb - e * P];
+        sv[e] = xa + xb;
+        dv[e] = xa - xb;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        int a, b;
+        fold_pair(*ax, i0 + e, a, b);
+        const float xa = a >= 0 ? x[a * P + col] : 0.f;
+        const float xb = b >= 0 ? x[b * P + col] : 0.f;
+        sv[e] = xa + xb;
+        dv[e] = b >= 0 ? xa - xb : 0.f;
+      }
+    }
+    float m = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) m = fmaxf(m, fmaxf(fabsf(sv[e]), fabsf(dv[e])));
+    m = row16_max(m);
+    int k = 15 - __builtin_amdgcn_frexp_expf(m);
+    k = k < -126 ? -126 : (k > 126 ? 126 : k);
+    const float sc = __builtin_amdgcn_ldexpf(1.f, k);
+    if ((threadIdx.x & 15) == 0) scl[col] = __builtin_amdgcn_ldexpf(1.f, -k);
+    unsigned s0[4], s1[4], d0[4], d1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      split2_f16(sv[2 * q], sv[2 * q + 1], sc, s0[q], s1[q]);
+      split2_f16(dv[2 * q], dv[2 * q + 1], sc, d0[q], d1[q]);
+    }
+    unsigned short* ps = fb + col * FBP + i0;
+    unsigned short* pd = ps + W * FBP;
+    *reinterpret_cast<uint4*>(ps) = make_uint4(s0[0], s0[1], s0[2], s0[3]);
+    *reinterpret_cast<uint4*>(ps + TS) = make_uint4(s1[0], s1[1], s1[2], s1[3]);
+    *reinterpret_cast<uint4*>(pd) = make_uint4(d0[0], d0[1], d0[2], d0[3]);
+    *reinterpret_cast<uint4*>(pd + TS) = make_uint4(d1[0], d1[1], d1[2], d1[3]);
   }
 
   __device__ __forceinline__ void operator()(float* buf, int S) {
-    const int n = g->n, pitch = g->pitch;
-    const int KS = ax->hK / 32;
-    const int tstride = 2 * W * ax->fb_pitch;
-    const bool isO = wave >= ax->RBe;
+    const int lane = threadIdx.x % 64;
     for (int s = 0; s < S; ++s) {
-      float* x = buf + s * n * pitch;
-      mf_fold_split<W>(x, pitch, *ax, fb);
+      float* x = buf + s * n * P;
+      fold(x);
       __syncthreads();
       f32x4 acc[2];
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (wave < ax->RB) {
-        const int half = isO ? 1 : 0;
+      if (mf) {
 #pragma unroll
         for (int ks = 0; ks < MF_KSMAX_F32; ++ks) {
           if (ks < KS) {
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
-              const unsigned short* bp = fb + (half * W + 16 * cb + lane % 16) * ax->fb_pitch +
-                                         32 * ks + 8 * (lane / 16);
-              const bf16x8 b0 = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(bp));
-              const bf16x8 b1 =
-                  __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(bp + tstride));
-              const bf16x8 b2 =
-                  __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(bp + 2 * tstride));
+              const unsigned short* bp = fb + bofs + 16 * cb * FBP + 32 * ks;
+              const f16x8 b0 = __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(bp));
+              const f16x8 b1 =
+                  __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(bp + TS));
               f32x4 c = acc[cb];
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][2], b0, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][1], b1, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][0], b2, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][1], b0, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][0], b1, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks][0], b0, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks][1], b0, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks][0], b1, c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks][0], b0, c, 0, 0, 0);
               acc[cb] = c;
             }
           }
         }
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          const float inv = scl[16 * cb + lane % 16];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[cb][r] *= inv;
+        }
       }
-      if (ax->direct) {
-        // DCT-I / DST-I: E row m is output 2m, O row m is output 2m + 1.
-        if (wave < ax->RB) {
-          const int mb = 16 * (isO ? wave - ax->RBe : wave) + 4 * (lane / 16);
+      if (direct) {
+        float* xr = x + xrow;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int k = 2 * (mb + r) + (isO ? 1 : 0);
-            if (k < n) {
+        for (int r = 0; r < 4; ++r) {
+          if (rmask & (1 << r)) {
 #pragma unroll
-              for (int cb = 0; cb < 2; ++cb) x[k * pitch + 16 * cb + lane % 16] = acc[cb][r];
-            }
+            for (int cb = 0; cb < 2; ++cb) xr[2 * r * P + 16 * cb] = acc[cb][r];
           }
         }
         __syncthreads();
       } else {
         float* R = reinterpret_cast<float*>(fb);
+        const int wave = threadIdx.x / 64;
         __syncthreads();
-        if (wave < ax->RB) {
+        if (mf) {
 #pragma unroll
           for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
@@ -241,7 +307,7 @@ struct MfmaXfF32 {
               R[(16 * wave + 4 * (lane / 16) + r) * ax->r_pitch + 16 * cb + lane % 16] = acc[cb][r];
         }
         __syncthreads();
-        mf_unfold<float, W>(R, *ax, n, x, pitch);
+        mf_unfold<float, W>(R, *ax, n, x, P);
         __syncthreads();
       }
     }

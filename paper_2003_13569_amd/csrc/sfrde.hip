@@ -312,20 +312,27 @@ MfmaTables mfma_tables(int bc, long long n) {
   return t;
 }
 
-// bf16 bits of x rounded to nearest even (x exactly representable in float
-// after the caller's rounding).
-unsigned short host_bf16(double x) {
-  float f = (float)x;
-  unsigned u;
-  memcpy(&u, &f, 4);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+// binary16 bits of x rounded to nearest even (subnormals included; |x| is
+// far below the binary16 maximum here).
+unsigned short host_f16(double x) {
+  const unsigned short sign = std::signbit(x) ? 0x8000 : 0;
+  const double a = std::fabs(x);
+  if (a <= std::ldexp(1.0, -25)) return sign;  // 2^-25 is the tie with 0
+  int e;
+  std::frexp(a, &e);  // a in [2^(e-1), 2^e)
+  int E = std::max(e - 1, -14);
+  double m = std::nearbyint(a / std::ldexp(1.0, E - 10));
+  if (m >= 2048.0) {
+    m *= 0.5;
+    E += 1;
+  }
+  if (m < 1024.0) return (unsigned short)(sign | (unsigned)m);  // subnormal
+  return (unsigned short)(sign | ((unsigned)(E + 15) << 10) | ((unsigned)m - 1024u));
 }
-double host_bf16_value(unsigned short h) {
-  unsigned u = (unsigned)h << 16;
-  float f;
-  memcpy(&f, &u, 4);
-  return (double)f;
+double host_f16_value(unsigned short h) {
+  const int ex = (h >> 10) & 31, man = h & 1023;
+  const double v = ex == 0 ? std::ldexp((double)man, -24) : std::ldexp((double)(man + 1024), ex - 25);
+  return (h & 0x8000) ? -v : v;
 }
 
 double half_entry(const MfmaTables& t, int rb, int row16, int k) {
@@ -360,13 +367,14 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   ax.hK = t.hK;
   ax.RBe = t.RBe;
   ax.RB = t.RB;
-  ax.fb_pitch = t.hK + (p->dtype == SFRDE_F32 ? 8 : 2);
+  ax.fb_pitch = p->dtype == SFRDE_F32 ? F32_FBP : t.hK + 2;
   ax.r_pitch = W + 1;
   ax.direct = p->bc != SFRDE_BC_PERIODIC;
   size_t tile_bytes = (size_t)p->S * g.n * g.pitch * p->w;
   tile_bytes = (tile_bytes + 15) / 16 * 16;
-  // fold area: FP32 plans keep three bf16 terms of s and d; FP64 plans s and d.
-  const size_t fold_bytes = p->dtype == SFRDE_F32 ? (size_t)3 * 2 * W * ax.fb_pitch * 2
+  // fold area: FP32 plans keep two binary16 terms of s and d and the column
+  // scales; FP64 plans s and d.
+  const size_t fold_bytes = p->dtype == SFRDE_F32 ? (size_t)f32_fold_bytes(W)
                                                    : (size_t)2 * W * ax.fb_pitch * 8;
   const size_t res_bytes = (size_t)16 * t.RB * ax.r_pitch * p->w;
   ax.fb_off = (int)tile_bytes;
@@ -377,20 +385,16 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   p->grid_m[axis] = (unsigned)std::min<long long>(g.ntiles, (long long)p->n_cu);
   // fragment-ordered split matrices
   if (p->dtype == SFRDE_F32) {
-    std::vector<unsigned short> frag((size_t)MF_WAVES * MF_KSMAX_F32 * 3 * 64 * 8, 0);
+    std::vector<unsigned short> frag((size_t)MF_WAVES * MF_KSMAX_F32 * 2 * 64 * 8, 0);
     for (int rb = 0; rb < t.RB; ++rb)
       for (int ks = 0; ks < MF_KSMAX_F32; ++ks)
         for (int lane = 0; lane < 64; ++lane)
           for (int e = 0; e < 8; ++e) {
             const double v = half_entry(t, rb, lane % 16, 32 * ks + 8 * (lane / 16) + e);
-            const unsigned short h0 = host_bf16(v);
-            const double r1 = v - host_bf16_value(h0);
-            const unsigned short h1 = host_bf16(r1);
-            const double r2 = r1 - host_bf16_value(h1);
-            const unsigned short h2 = host_bf16(r2);
-            const unsigned short hs[3] = {h0, h1, h2};
-            for (int tt = 0; tt < 3; ++tt)
-              frag[((((size_t)rb * MF_KSMAX_F32 + ks) * 3 + tt) * 64 + lane) * 8 + e] = hs[tt];
+            const unsigned short h0 = host_f16(v);
+            const unsigned short h1 = host_f16(v - host_f16_value(h0));
+            frag[((((size_t)rb * MF_KSMAX_F32 + ks) * 2 + 0) * 64 + lane) * 8 + e] = h0;
+            frag[((((size_t)rb * MF_KSMAX_F32 + ks) * 2 + 1) * 64 + lane) * 8 + e] = h1;
           }
     TRY(dev_alloc(p, &p->mf_A[axis], frag.size() * sizeof(unsigned short)));
     HIPCHECK(hipMemcpy(p->mf_A[axis], frag.data(), frag.size() * sizeof(unsigned short),
