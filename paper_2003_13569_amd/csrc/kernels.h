@@ -387,6 +387,7 @@ struct StageArgs {
   T* P;             // in/out fields [S][total]
   const T* src;     // Z kernel: load from here and skip the forward transform
   const T* coef;    // [6][S][total]
+  const T* ltab;    // [S][total] L values: P13 coefficients formed in the combine, or null
   const T* dcoef;   // [6][S][total] (adjoint parameter sensitivities)
   T* uhat;          // forward retained arrays
   T* ctil;
@@ -404,6 +405,7 @@ struct StageArgs {
   Rxn rxn;
   double t;
   T cs;             // product of the per-axis inverse scales
+  T tau;            // time step
   int S;
   int mode;         // stage 0..3, or MODE_INIT / MODE_RESTORE
   int last;         // adjoint: this is step 0 (output u-bar, not phi3 u-bar)
@@ -446,6 +448,71 @@ __device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long 
   return bad;
 }
 
+// Coefficients a forward stage needs, as c0..c3:
+//   stage 0: Q, phi, R, phi1;  stage 1: Q, phi, phi2;  stage 2: -, phi, phi2;
+//   stage 3: -, -, phi3.
+template <typename T>
+__device__ __forceinline__ T recip(T x) {
+  return T(1) / x;
+}
+template <>
+__device__ __forceinline__ float recip<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+
+// P13 coefficients (Section 4) of one L in the field precision. The
+// denominators D = 24 + 18L + 6L^2 + L^3 and Dh = 192 + 72L + 12L^2 + L^3 are
+// sums of positive terms for L >= 0. R13 and Q13 multiply the retained
+// spectral state every step, so for L < 1 they are formed as
+//   R13 = 1 - L (24 + 6L + L^2) / D,   Q13 = 1 - L (96 + 12L + L^2) / Dh,
+// exact at L = 0 (the mean of a Neumann or periodic field is not damped by a
+// rounded reciprocal) and accurate to the rounding of 1 for small L. FP32
+// tables clamp L far below overflow of L^3.
+template <typename T>
+__device__ __forceinline__ void stage_coefs_L(int mode, T L, T tau, T& c0, T& c1, T& c2, T& c3) {
+  const T iD = recip<T>(T(24) + L * (T(18) + L * (T(6) + L)));
+  if (mode == 3) {
+    c2 = tau * (T(4) + L * (T(3) + L)) * iD;
+    return;
+  }
+  const bool small = L < T(1);
+  const T iDh = recip<T>(T(192) + L * (T(72) + L * (T(12) + L)));
+  const T ph = T(96) + L * (T(12) + L);
+  c1 = tau * ph * iDh;
+  if (mode <= 1) c0 = small ? T(1) - L * ph * iDh : T(24) * (T(8) - L) * iDh;
+  if (mode != 0) {
+    c2 = T(2) * tau * (T(4) + L) * iD;
+    return;
+  }
+  c2 = small ? T(1) - L * (T(24) + L * (T(6) + L)) * iD : (T(24) - T(6) * L) * iD;
+  c3 = tau * (T(4) - L) * iD;
+}
+
+template <typename T>
+__device__ __forceinline__ void stage_coefs_tab(int mode, const T* cf, long long cst, T& c0, T& c1,
+                                                T& c2, T& c3) {
+  switch (mode) {
+    case 0:
+      c0 = cf[C_Q * cst];
+      c1 = cf[C_PHI * cst];
+      c2 = cf[C_R * cst];
+      c3 = cf[C_PHI1 * cst];
+      break;
+    case 1:
+      c0 = cf[C_Q * cst];
+      c1 = cf[C_PHI * cst];
+      c2 = cf[C_PHI2 * cst];
+      break;
+    case 2:
+      c1 = cf[C_PHI * cst];
+      c2 = cf[C_PHI2 * cst];
+      break;
+    default:
+      c2 = cf[C_PHI3 * cst];
+      break;
+  }
+}
+
 // Forward stage combine: buf holds the transformed reaction (full spectral);
 // replaced by cs times the next stage's spectral value.
 template <typename T>
@@ -465,36 +532,40 @@ __device__ __forceinline__ void pw_combine(const StageArgs<T>& a, T* buf, long l
       T& cell = buf[(s * g.n + j) * g.pitch + w];
       const T fh = cell;
       const long long i = s * tot + idx;
-      const T* cf = a.coef + i;  // coefficient q at cf[q * cst]
-      T out;
+      T out, c0 = T(0), c1 = T(0), c2 = T(0), c3 = T(0);
+      if (a.mode <= 3) {
+        if (a.ltab)
+          stage_coefs_L<T>(a.mode, a.ltab[i], a.tau, c0, c1, c2, c3);
+        else
+          stage_coefs_tab<T>(a.mode, a.coef + i, cst, c0, c1, c2, c3);
+      }
       switch (a.mode) {
         case 0: {
           const T uh = a.uhat[i];
           if (a.st_uhat) a.st_uhat[i] = uh;
           if (a.st_fhat) a.st_fhat[i] = fh;
-          const T cQ = cf[C_Q * cst], cP = cf[C_PHI * cst];
-          const T av = cQ * uh + cP * fh;
-          a.ctil[i] = cQ * av - cP * fh;
-          a.acc[i] = cf[C_R * cst] * uh + cf[C_PHI1 * cst] * fh;
+          const T av = c0 * uh + c1 * fh;
+          a.ctil[i] = c0 * av - c1 * fh;
+          a.acc[i] = c2 * uh + c3 * fh;
           out = av;
           break;
         }
         case 1: {
           if (a.st_fhat) a.st_fhat[1 * cst + i] = fh;
           const T uh = a.uhat[i];
-          out = cf[C_Q * cst] * uh + cf[C_PHI * cst] * fh;
-          a.acc[i] += cf[C_PHI2 * cst] * fh;
+          out = c0 * uh + c1 * fh;
+          a.acc[i] += c2 * fh;
           break;
         }
         case 2: {
           if (a.st_fhat) a.st_fhat[2 * cst + i] = fh;
-          out = a.ctil[i] + T(2) * cf[C_PHI * cst] * fh;
-          a.acc[i] += cf[C_PHI2 * cst] * fh;
+          out = a.ctil[i] + T(2) * c1 * fh;
+          a.acc[i] += c2 * fh;
           break;
         }
         case 3: {
           if (a.st_fhat) a.st_fhat[3 * cst + i] = fh;
-          const T un = a.acc[i] + cf[C_PHI3 * cst] * fh;
+          const T un = a.acc[i] + c2 * fh;
           a.uhat[i] = un;
           out = un;
           break;
@@ -514,7 +585,83 @@ __device__ __forceinline__ void pw_combine(const StageArgs<T>& a, T* buf, long l
 
 // Vectorised forward combine for full tiles along a strided axis: each work
 // item is VW consecutive lanes of one row of one species, with all of its
-// global loads issued before the arithmetic. Falls back to pw_combine.
+// global loads issued before the arithmetic. One instance per stage.
+template <typename T, int MODE, bool LT>
+__device__ __forceinline__ void combine_vec(const StageArgs<T>& a, T* buf, const TileRef& tr) {
+  using V = typename Vec16<T>::type;
+  constexpr int VW = Vec16<T>::N;
+  const Geom& g = a.g;
+  const int S = a.S;
+  const long long tot = g.total;
+  const long long cst = (long long)S * tot;
+  const int ngroups = g.n * g.W / VW;
+  const T cs = a.cs;
+#pragma clang loop unroll(disable)
+  for (int it = threadIdx.x; it < S * ngroups; it += blockDim.x) {
+    const int s = it >= ngroups ? (it >= 2 * ngroups ? (it >= 3 * ngroups ? 3 : 2) : 1) : 0;
+    long long gi;
+    int j, w;
+    vec_coords<T>(g, tr, it - s * ngroups, gi, j, w);
+    const long long i = s * tot + gi;
+    T* cell = buf + (s * g.n + j) * g.pitch + w;
+    // global loads first
+    V Lv, t0, t1, t2, t3, uh, ac, ct;
+    if (LT) {
+      Lv = *reinterpret_cast<const V*>(a.ltab + i);
+    } else {
+      const T* cf = a.coef + i;
+      if (MODE <= 1) t0 = *reinterpret_cast<const V*>(cf + C_Q * cst);
+      if (MODE <= 2) t1 = *reinterpret_cast<const V*>(cf + C_PHI * cst);
+      t2 = *reinterpret_cast<const V*>(cf + (MODE == 0 ? C_R : MODE == 3 ? C_PHI3 : C_PHI2) * cst);
+      if (MODE == 0) t3 = *reinterpret_cast<const V*>(cf + C_PHI1 * cst);
+    }
+    if (MODE <= 1) uh = *reinterpret_cast<const V*>(a.uhat + i);
+    if (MODE >= 1) ac = *reinterpret_cast<const V*>(a.acc + i);
+    if (MODE == 2) ct = *reinterpret_cast<const V*>(a.ctil + i);
+    V fh, o0, o1, out;
+    for (int e = 0; e < VW; ++e) vset<T>(fh, e, cell[e]);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      T c0 = T(0), c1 = T(0), c2 = T(0), c3 = T(0);
+      if (LT) {
+        stage_coefs_L<T>(MODE, vget<T>(Lv, e), a.tau, c0, c1, c2, c3);
+      } else {
+        if (MODE <= 1) c0 = vget<T>(t0, e);
+        if (MODE <= 2) c1 = vget<T>(t1, e);
+        c2 = vget<T>(t2, e);
+        if (MODE == 0) c3 = vget<T>(t3, e);
+      }
+      const T f = vget<T>(fh, e);
+      if (MODE == 0) {
+        const T u = vget<T>(uh, e);
+        const T av = c0 * u + c1 * f;
+        vset<T>(o0, e, c0 * av - c1 * f);
+        vset<T>(o1, e, c2 * u + c3 * f);
+        vset<T>(out, e, cs * av);
+      } else if (MODE == 1) {
+        vset<T>(out, e, cs * (c0 * vget<T>(uh, e) + c1 * f));
+        vset<T>(o1, e, vget<T>(ac, e) + c2 * f);
+      } else if (MODE == 2) {
+        vset<T>(out, e, cs * (vget<T>(ct, e) + T(2) * c1 * f));
+        vset<T>(o1, e, vget<T>(ac, e) + c2 * f);
+      } else {
+        const T un = vget<T>(ac, e) + c2 * f;
+        vset<T>(o0, e, un);
+        vset<T>(out, e, cs * un);
+      }
+    }
+    if (MODE == 0) {
+      if (a.st_uhat) *reinterpret_cast<V*>(a.st_uhat + i) = uh;
+      *reinterpret_cast<V*>(a.ctil + i) = o0;
+    }
+    if (a.st_fhat) *reinterpret_cast<V*>(a.st_fhat + MODE * cst + i) = fh;
+    if (MODE <= 2) *reinterpret_cast<V*>(a.acc + i) = o1;
+    if (MODE == 3) *reinterpret_cast<V*>(a.uhat + i) = o0;
+    for (int e = 0; e < VW; ++e) cell[e] = vget<T>(out, e);
+  }
+}
+
+// Forward combine of a tile; full tiles along strided axes move in vectors.
 template <typename T>
 __device__ __forceinline__ void pw_combine_fast(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
@@ -523,78 +670,20 @@ __device__ __forceinline__ void pw_combine_fast(const StageArgs<T>& a, T* buf, l
     pw_combine(a, buf, tile);
     return;
   }
-  using V = typename Vec16<T>::type;
-  constexpr int VW = Vec16<T>::N;
-  const int S = a.S;
-  const long long tot = g.total;
-  const long long cst = (long long)S * tot;
-  const int ngroups = g.n * g.W / VW;
-  const int mode = a.mode;
-  const T cs = a.cs;
-  for (int it = threadIdx.x; it < S * ngroups; it += blockDim.x) {
-    const int s = it >= ngroups ? (it >= 2 * ngroups ? (it >= 3 * ngroups ? 3 : 2) : 1) : 0;
-    long long gi;
-    int j, w;
-    vec_coords<T>(g, tr, it - s * ngroups, gi, j, w);
-    const long long i = s * tot + gi;
-    const T* cf = a.coef + i;
-    T* cell = buf + (s * g.n + j) * g.pitch + w;
-    V fh, o0, o1, out;
-    for (int e = 0; e < VW; ++e) vset<T>(fh, e, cell[e]);
-    if (mode == 0) {
-      const V uh = *reinterpret_cast<const V*>(a.uhat + i);
-      const V cQ = *reinterpret_cast<const V*>(cf + C_Q * cst);
-      const V cP = *reinterpret_cast<const V*>(cf + C_PHI * cst);
-      const V cR = *reinterpret_cast<const V*>(cf + C_R * cst);
-      const V c1 = *reinterpret_cast<const V*>(cf + C_PHI1 * cst);
-      for (int e = 0; e < VW; ++e) {
-        const T f = vget<T>(fh, e), u = vget<T>(uh, e), q = vget<T>(cQ, e), p = vget<T>(cP, e);
-        const T av = q * u + p * f;
-        vset<T>(o0, e, q * av - p * f);
-        vset<T>(o1, e, vget<T>(cR, e) * u + vget<T>(c1, e) * f);
-        vset<T>(out, e, cs * av);
-      }
-      if (a.st_uhat) *reinterpret_cast<V*>(a.st_uhat + i) = uh;
-      if (a.st_fhat) *reinterpret_cast<V*>(a.st_fhat + i) = fh;
-      *reinterpret_cast<V*>(a.ctil + i) = o0;
-      *reinterpret_cast<V*>(a.acc + i) = o1;
-    } else if (mode == 1) {
-      const V uh = *reinterpret_cast<const V*>(a.uhat + i);
-      const V ac = *reinterpret_cast<const V*>(a.acc + i);
-      const V cQ = *reinterpret_cast<const V*>(cf + C_Q * cst);
-      const V cP = *reinterpret_cast<const V*>(cf + C_PHI * cst);
-      const V c2 = *reinterpret_cast<const V*>(cf + C_PHI2 * cst);
-      for (int e = 0; e < VW; ++e) {
-        const T f = vget<T>(fh, e);
-        vset<T>(out, e, cs * (vget<T>(cQ, e) * vget<T>(uh, e) + vget<T>(cP, e) * f));
-        vset<T>(o1, e, vget<T>(ac, e) + vget<T>(c2, e) * f);
-      }
-      if (a.st_fhat) *reinterpret_cast<V*>(a.st_fhat + cst + i) = fh;
-      *reinterpret_cast<V*>(a.acc + i) = o1;
-    } else if (mode == 2) {
-      const V ct = *reinterpret_cast<const V*>(a.ctil + i);
-      const V ac = *reinterpret_cast<const V*>(a.acc + i);
-      const V cP = *reinterpret_cast<const V*>(cf + C_PHI * cst);
-      const V c2 = *reinterpret_cast<const V*>(cf + C_PHI2 * cst);
-      for (int e = 0; e < VW; ++e) {
-        const T f = vget<T>(fh, e);
-        vset<T>(out, e, cs * (vget<T>(ct, e) + T(2) * vget<T>(cP, e) * f));
-        vset<T>(o1, e, vget<T>(ac, e) + vget<T>(c2, e) * f);
-      }
-      if (a.st_fhat) *reinterpret_cast<V*>(a.st_fhat + 2 * cst + i) = fh;
-      *reinterpret_cast<V*>(a.acc + i) = o1;
-    } else {
-      const V ac = *reinterpret_cast<const V*>(a.acc + i);
-      const V c3 = *reinterpret_cast<const V*>(cf + C_PHI3 * cst);
-      for (int e = 0; e < VW; ++e) {
-        const T un = vget<T>(ac, e) + vget<T>(c3, e) * vget<T>(fh, e);
-        vset<T>(o0, e, un);
-        vset<T>(out, e, cs * un);
-      }
-      if (a.st_fhat) *reinterpret_cast<V*>(a.st_fhat + 3 * cst + i) = fh;
-      *reinterpret_cast<V*>(a.uhat + i) = o0;
-    }
-    for (int e = 0; e < VW; ++e) cell[e] = vget<T>(out, e);
+  const bool lt = a.ltab != nullptr;
+  switch (a.mode) {
+    case 0:
+      lt ? combine_vec<T, 0, true>(a, buf, tr) : combine_vec<T, 0, false>(a, buf, tr);
+      break;
+    case 1:
+      lt ? combine_vec<T, 1, true>(a, buf, tr) : combine_vec<T, 1, false>(a, buf, tr);
+      break;
+    case 2:
+      lt ? combine_vec<T, 2, true>(a, buf, tr) : combine_vec<T, 2, false>(a, buf, tr);
+      break;
+    default:
+      lt ? combine_vec<T, 3, true>(a, buf, tr) : combine_vec<T, 3, false>(a, buf, tr);
+      break;
   }
 }
 
@@ -966,6 +1055,14 @@ __global__ void k_coefs(CoefArgs c, T* out) {
     const double lam = lambda_at(c, idx);
     for (int s = 0; s < c.S; ++s) {
       const double L = lam > 0.0 ? c.kappa[s] * c.tau * pow(lam, 0.5 * c.alpha[s]) : 0.0;
+      if (c.deriv == 2) {
+        // L itself. FP32 tables clamp it at 1e12 so that L^3 stays finite;
+        // there every P13 coefficient is at most about tau / L, far below
+        // the FP32 resolution of the terms it is added to.
+        const double Lc = sizeof(T) == 4 && L > 1e12 ? 1e12 : L;
+        out[(long long)s * c.total + idx] = T(Lc);
+        continue;
+      }
       double v[NCOEF];
       if (c.deriv)
         coef_derivs(c.scheme, L, c.tau, v);

@@ -91,6 +91,7 @@ struct sfrde_plan_s {
   double* lam[3] = {nullptr, nullptr, nullptr};
   void* coef = nullptr;
   void* dcoef = nullptr;
+  void* ltab = nullptr;  // P13 plans: L per species and point
   void* P = nullptr;
   void* uhat = nullptr;
   void* ctil = nullptr;
@@ -438,7 +439,9 @@ StageArgs<T> stage_args(sfrde_plan_s* p, int axis, void* P) {
   a.Mt = (const T*)p->Mt[axis];
   a.P = (T*)P;
   a.coef = (const T*)p->coef;
+  a.ltab = (const T*)p->ltab;
   a.dcoef = (const T*)p->dcoef;
+  a.tau = T(p->dt);
   a.uhat = (T*)p->uhat;
   a.ctil = (T*)p->ctil;
   a.acc = (T*)p->acc;
@@ -861,7 +864,7 @@ void destroy_plan(sfrde_plan_s* p) {
   if (!p) return;
   (void)hipStreamSynchronize(p->stream);
   void** ptrs[] = {&p->Mt[0], &p->Mt[1], &p->Mt[2], (void**)&p->lam[0], (void**)&p->lam[1],
-                   (void**)&p->lam[2], &p->coef, &p->dcoef, &p->P, &p->uhat, &p->ctil, &p->acc,
+                   (void**)&p->lam[2], &p->coef, &p->dcoef, &p->ltab, &p->P, &p->uhat, &p->ctil, &p->acc,
                    &p->Pa, &p->zh, &p->aacc, &p->ahat, &p->gu, (void**)&p->G, &p->seg,
                    (void**)&p->rp_acc, (void**)&p->red, (void**)&p->flag, &p->mf_A[0],
                    &p->mf_A[1], &p->mf_A[2]};
@@ -980,6 +983,20 @@ int build_plan(sfrde_plan_s* p) {
     hipLaunchKernelGGL(k_coefs<double>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
                        (double*)p->coef);
   HIPCHECK(hipGetLastError());
+  if (p->scheme == SFRDE_SCHEME_P13) {
+    // The forward combine forms the P13 coefficients from L: one table read
+    // per species and stage instead of up to four. The six tables stay for
+    // the adjoint.
+    TRY(dev_alloc(p, &p->ltab, f));
+    c.deriv = 2;
+    if (p->dtype == SFRDE_F32)
+      hipLaunchKernelGGL(k_coefs<float>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
+                         (float*)p->ltab);
+    else
+      hipLaunchKernelGGL(k_coefs<double>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream,
+                         c, (double*)p->ltab);
+    HIPCHECK(hipGetLastError());
+  }
   TRY(fill<int>(p, p->flag, 16, 0));
   HIPCHECK(hipStreamSynchronize(p->stream));
   return SFRDE_OK;

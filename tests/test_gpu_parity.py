@@ -157,6 +157,21 @@ def test_single_eigenmode_decays_by_R13_power(bc):
     assert np.max(np.abs(got - R ** M * u0)) <= 1e-12
 
 
+@pytest.mark.parametrize("bc", ["periodic", "neumann"])
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("f64", 1e-13)])
+def test_mean_mode_is_not_damped(bc, dtype, tol):
+    # f = 0 and a constant field: L = 0 on the constant mode, where R13 = 1
+    # exactly (Section 4), so the field stays constant over any number of
+    # steps. A multiplier off by one rounding of 1 would drift by 500 ulps.
+    wl = W.Workload(name="mean", bc=bc, shape=(20, 24, 28), domain=(0.0, 1.0), alpha=(1.5,),
+                    kappa=(0.7,), reaction="linear", params=(0.0,), dt=0.005, nsteps=500, seed=0,
+                    init="normal")
+    c = 0.9359
+    u0 = np.full((1,) + wl.shape, c)
+    got = run(wl, u0, wl.nsteps, dtype)
+    assert np.max(np.abs(got - c)) <= tol * c
+
+
 def test_nonfinite_reaction_is_reported():
     wl = CASES[2]
     u0 = W.initial_fields(wl)
