@@ -37,6 +37,8 @@ constexpr int KMAX = 32;  // outputs per thread in the dense transform: n*W <= K
 
 struct Geom {
   int n;            // length of the transformed axis
+  int spt;          // species per tile: all, or 1 (strided axes may split tiles by species,
+                    // with the species index folded into the outer blocks)
   int W;            // lines per tile (a power of two)
   int pitch;        // LDS row pitch (>= W)
   int wshift;       // log2(W)
@@ -369,7 +371,7 @@ __device__ __forceinline__ double point_weight(long long idx, long long n0, long
   long long i0 = idx % n0;
   long long r = idx / n0;
   long long i1 = r % n1;
-  long long i2 = r / n1;
+  long long i2 = (r / n1) % n2;  // species-split tiles index past the first species
   double w = 1.0;
   if (i0 == 0 || i0 == n0 - 1) w *= 0.5;
   if (i1 == 0 || i1 == n1 - 1) w *= 0.5;
@@ -528,7 +530,7 @@ __device__ __forceinline__ void pw_combine(const StageArgs<T>& a, T* buf, long l
     unpack(g, e, j, w);
     long long idx;
     if (!elem(g, tr, j, w, idx)) continue;
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < g.spt; ++s) {
       T& cell = buf[(s * g.n + j) * g.pitch + w];
       const T fh = cell;
       const long long i = s * tot + idx;
@@ -597,7 +599,7 @@ __device__ __forceinline__ void combine_vec(const StageArgs<T>& a, T* buf, const
   const int ngroups = g.n * g.W / VW;
   const T cs = a.cs;
 #pragma clang loop unroll(disable)
-  for (int it = threadIdx.x; it < S * ngroups; it += blockDim.x) {
+  for (int it = threadIdx.x; it < g.spt * ngroups; it += blockDim.x) {
     const int s = it >= ngroups ? (it >= 2 * ngroups ? (it >= 3 * ngroups ? 3 : 2) : 1) : 0;
     long long gi;
     int j, w;
@@ -737,7 +739,7 @@ __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, lo
     unpack(g, e, j, w);
     long long idx;
     if (!elem(g, tr, j, w, idx)) continue;
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < g.spt; ++s) {
       T& cell = buf[(s * g.n + j) * g.pitch + w];
       const T X = cell;
       const long long i = s * tot + idx;
@@ -835,90 +837,90 @@ __device__ __forceinline__ void tile_out(const Geom& g, long long tile, const T*
 
 template <bool FAST, typename T, class XF>
 __device__ __forceinline__ void body_x(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
-  tile_in<FAST>(a.g, tile, a.P, buf, a.S);
+  tile_in<FAST>(a.g, tile, a.P, buf, a.g.spt);
   __syncthreads();
-  xf(buf, a.S);
+  xf(buf, a.g.spt);
   const bool bad = pw_reaction(a, buf, tile);
   if (bad) a.flag[0] = 1;
   __syncthreads();
-  xf(buf, a.S);
-  tile_out<FAST>(a.g, tile, buf, a.P, a.S);
+  xf(buf, a.g.spt);
+  tile_out<FAST>(a.g, tile, buf, a.P, a.g.spt);
 }
 
 template <bool FAST, typename T, class XF>
 __device__ __forceinline__ void body_z(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
-  tile_in<FAST>(a.g, tile, a.src ? a.src : a.P, buf, a.S);
+  tile_in<FAST>(a.g, tile, a.src ? a.src : a.P, buf, a.g.spt);
   __syncthreads();
-  if (!a.src) xf(buf, a.S);
+  if (!a.src) xf(buf, a.g.spt);
   if (FAST)
     pw_combine_fast(a, buf, tile);
   else
     pw_combine(a, buf, tile);
   __syncthreads();
-  xf(buf, a.S);
-  tile_out<FAST>(a.g, tile, buf, a.P, a.S);
+  xf(buf, a.g.spt);
+  tile_out<FAST>(a.g, tile, buf, a.P, a.g.spt);
 }
 
 template <bool FAST, typename T, class XF>
 __device__ __forceinline__ void body_xadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf,
                                           double* pacc) {
-  tile_in<FAST>(a.g, tile, a.P, buf, a.S);
+  tile_in<FAST>(a.g, tile, a.P, buf, a.g.spt);
   __syncthreads();
-  xf(buf, a.S);
+  xf(buf, a.g.spt);
   pw_adj_reaction(a, buf, tile, pacc);
   __syncthreads();
-  xf(buf, a.S);
-  tile_out<FAST>(a.g, tile, buf, a.P, a.S);
+  xf(buf, a.g.spt);
+  tile_out<FAST>(a.g, tile, buf, a.P, a.g.spt);
 }
 
 template <bool FAST, typename T, class XF>
 __device__ __forceinline__ void body_zadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
-  tile_in<FAST>(a.g, tile, a.P, buf, a.S);
+  tile_in<FAST>(a.g, tile, a.P, buf, a.g.spt);
   __syncthreads();
-  xf(buf, a.S);
+  xf(buf, a.g.spt);
   pw_adj_combine(a, buf, tile);
   __syncthreads();
-  xf(buf, a.S);
-  tile_out<FAST>(a.g, tile, buf, a.P, a.S);
+  xf(buf, a.g.spt);
+  tile_out<FAST>(a.g, tile, buf, a.P, a.g.spt);
 }
 
 // Bodies for tiles already staged in LDS (persistent kernels load ahead).
 template <typename T, class XF>
 __device__ __forceinline__ void run_x(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
-  xf(buf, a.S);
+  xf(buf, a.g.spt);
   const bool bad = pw_reaction(a, buf, tile);
   if (bad) a.flag[0] = 1;
   __syncthreads();
-  xf(buf, a.S);
-  store_tile_fast(a.g, tile, buf, a.P, a.S);
+  xf(buf, a.g.spt);
+  store_tile_fast(a.g, tile, buf, a.P, a.g.spt);
 }
 
 template <typename T, class XF>
 __device__ __forceinline__ void run_z(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
-  if (!a.src) xf(buf, a.S);
+  if (!a.src) xf(buf, a.g.spt);
   pw_combine_fast(a, buf, tile);
   __syncthreads();
-  xf(buf, a.S);
-  store_tile_fast(a.g, tile, buf, a.P, a.S);
+  xf(buf, a.g.spt);
+  store_tile_fast(a.g, tile, buf, a.P, a.g.spt);
 }
 
 template <typename T, class XF>
 __device__ __forceinline__ void run_xadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf,
                                          double* pacc) {
-  xf(buf, a.S);
+  xf(buf, a.g.spt);
   pw_adj_reaction(a, buf, tile, pacc);
   __syncthreads();
-  xf(buf, a.S);
-  store_tile_fast(a.g, tile, buf, a.P, a.S);
+  xf(buf, a.g.spt);
+  store_tile_fast(a.g, tile, buf, a.P, a.g.spt);
 }
 
 template <typename T, class XF>
 __device__ __forceinline__ void run_zadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
-  xf(buf, a.S);
+  xf(buf, a.g.spt);
   pw_adj_combine(a, buf, tile);
   __syncthreads();
-  xf(buf, a.S);
-  store_tile_fast(a.g, tile, buf, a.P, a.S);
+  xf(buf, a.g.spt);
+  store_tile_fast(a.g, tile, buf, a.P, a.g.spt);
 }
 
 // Dense transform as a functor (one tile per block).

@@ -152,25 +152,33 @@ __device__ __forceinline__ float row16_max(float m) {
   return m;
 }
 
+// Eight waves; wave w owns row blocks 2w and 2w + 1 (of E, then of O), so
+// two 512-thread blocks share a CU and one block's memory waits overlap the
+// other's arithmetic. W = 32 lines for strided axes (128-byte rows), 16 for
+// the contiguous x axis (whose tiles hold every species).
+template <int W_>
 struct MfmaXfF32 {
-  static constexpr int W = 32;
+  static constexpr int W = W_;
+  static constexpr int THREADS = 512;
   static constexpr int P = W + 1;             // LDS row pitch of the tile
   static constexpr int FBP = F32_FBP;
   static constexpr int TS = 2 * W * F32_FBP;  // binary16 elements between the two terms
   static constexpr int FOLD_THREADS = 16 * W; // one 16-lane row per column
+  static constexpr int CB = W / 16;           // 16-column blocks
   const MfmaAxisDev* ax;
   unsigned short* fb;
   float* scl;  // inverse column scales
-  f16x8 A[MF_KSMAX_F32][2];
+  f16x8 A[2][MF_KSMAX_F32][2];
   int n, KS;
-  bool mf;     // this wave owns a row block
+  int nrb;      // row blocks of this wave (0..2)
+  bool shareB;  // both row blocks read the same fold half
   bool direct;
-  int bofs;    // this lane's B-fragment offset in fb
+  int bofs[2];  // B-fragment offsets in fb per row block
   // fold work item of this thread: column col, entries i0 .. i0+7
   bool ffast;
   int i0, col, fa, fbb;
-  // output rows of this lane's results (direct unfold)
-  int xrow, rmask;
+  // output rows of this lane's results (direct unfold), per row block
+  int xrow[2], rmask[2];
 
   __device__ __forceinline__ MfmaXfF32(const Geom*, const MfmaAxisDev* ax_, float* fb_)
       : ax(ax_), fb(reinterpret_cast<unsigned short*>(fb_)) {
@@ -178,19 +186,35 @@ struct MfmaXfF32 {
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     n = ax->n;
     KS = ax->hK >> 5;
-    mf = wave < ax->RB;
     direct = ax->direct != 0;
+    const int rb0 = 2 * wave;
+    nrb = ax->RB - rb0;
+    nrb = nrb < 0 ? 0 : (nrb > 2 ? 2 : nrb);
     const uint4* src = reinterpret_cast<const uint4*>(ax->Afrag);
+    bool isO[2];
 #pragma unroll
-    for (int ks = 0; ks < MF_KSMAX_F32; ++ks)
+    for (int h = 0; h < 2; ++h) {
+      const int rb = rb0 + h;
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (mf) v = src[((wave * MF_KSMAX_F32 + ks) * 2 + t) * 64 + lane];
-        A[ks][t] = __builtin_bit_cast(f16x8, v);
-      }
-    const bool isO = wave >= ax->RBe;
-    bofs = ((isO ? W : 0) + lane % 16) * FBP + 8 * (lane / 16);
+      for (int ks = 0; ks < MF_KSMAX_F32; ++ks)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          uint4 v = make_uint4(0, 0, 0, 0);
+          if (h < nrb) v = src[((rb * MF_KSMAX_F32 + ks) * 2 + t) * 64 + lane];
+          A[h][ks][t] = __builtin_bit_cast(f16x8, v);
+        }
+      isO[h] = rb >= ax->RBe;
+      bofs[h] = ((isO[h] ? W : 0) + lane % 16) * FBP + 8 * (lane / 16);
+      // direct unfold: E row m -> output 2m, O row m -> output 2m + 1
+      const int mb = 16 * (isO[h] ? rb - ax->RBe : rb) + 4 * (lane / 16);
+      const int row0 = 2 * mb + (isO[h] ? 1 : 0);
+      xrow[h] = row0 * P + lane % 16;
+      rmask[h] = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (h < nrb && row0 + 2 * r < n) rmask[h] |= 1 << r;
+    }
+    shareB = nrb < 2 || isO[0] == isO[1];
     // fold item; entries past the folded length come out as zeros
     col = (threadIdx.x >> 4) & (W - 1);
     i0 = (threadIdx.x & 15) << 3;
@@ -198,14 +222,6 @@ struct MfmaXfF32 {
     ffast = ax->periodic ? (i0 >= 1 && 2 * (i0 + 7) < n) : (2 * (i0 + 7) + 1 < n);
     fa = i0 * P + col;
     fbb = (bstart - i0) * P + col;
-    // direct unfold: E row m -> output 2m, O row m -> output 2m + 1
-    const int mb = 16 * (isO ? wave - ax->RBe : wave) + 4 * (lane / 16);
-    const int row0 = 2 * mb + (isO ? 1 : 0);
-    xrow = row0 * P + lane % 16;
-    rmask = 0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (mf && row0 + 2 * r < n) rmask |= 1 << r;
   }
 
   __device__ __forceinline__ void fold(const float* x) {
@@ -251,60 +267,83 @@ struct MfmaXfF32 {
     *reinterpret_cast<uint4*>(pd + TS) = make_uint4(d1[0], d1[1], d1[2], d1[3]);
   }
 
+  __device__ __forceinline__ static f16x8 frag(const unsigned short* p) {
+    return __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(p));
+  }
+
+  __device__ __forceinline__ void products(f32x4 (&acc)[2][CB]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[h][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (nrb == 0) return;
+#pragma unroll
+    for (int ks = 0; ks < MF_KSMAX_F32; ++ks) {
+      if (ks >= KS) break;
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) {
+        const int off = 16 * cb * FBP + 32 * ks;
+        f16x8 b0 = frag(fb + bofs[0] + off), b1 = frag(fb + bofs[0] + off + TS);
+        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[0][ks][1], b0, acc[0][cb], 0, 0, 0);
+        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[0][ks][0], b1, acc[0][cb], 0, 0, 0);
+        acc[0][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[0][ks][0], b0, acc[0][cb], 0, 0, 0);
+        if (nrb == 2) {
+          if (!shareB) {
+            b0 = frag(fb + bofs[1] + off);
+            b1 = frag(fb + bofs[1] + off + TS);
+          }
+          acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[1][ks][1], b0, acc[1][cb], 0, 0, 0);
+          acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[1][ks][0], b1, acc[1][cb], 0, 0, 0);
+          acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[1][ks][0], b0, acc[1][cb], 0, 0, 0);
+        }
+      }
+    }
+    const int lane = threadIdx.x % 64;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const float inv = scl[16 * cb + lane % 16];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[h][cb][r] *= inv;
+    }
+  }
+
   __device__ __forceinline__ void operator()(float* buf, int S) {
     const int lane = threadIdx.x % 64;
     for (int s = 0; s < S; ++s) {
       float* x = buf + s * n * P;
       fold(x);
       __syncthreads();
-      f32x4 acc[2];
-#pragma unroll
-      for (int cb = 0; cb < 2; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-      if (mf) {
-#pragma unroll
-        for (int ks = 0; ks < MF_KSMAX_F32; ++ks) {
-          if (ks < KS) {
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-              const unsigned short* bp = fb + bofs + 16 * cb * FBP + 32 * ks;
-              const f16x8 b0 = __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(bp));
-              const f16x8 b1 =
-                  __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4*>(bp + TS));
-              f32x4 c = acc[cb];
-              c = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks][1], b0, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks][0], b1, c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[ks][0], b0, c, 0, 0, 0);
-              acc[cb] = c;
-            }
-          }
-        }
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          const float inv = scl[16 * cb + lane % 16];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[cb][r] *= inv;
-        }
-      }
+      f32x4 acc[2][CB];
+      products(acc);
       if (direct) {
-        float* xr = x + xrow;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (rmask & (1 << r)) {
+        for (int h = 0; h < 2; ++h) {
+          float* xr = x + xrow[h];
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb) xr[2 * r * P + 16 * cb] = acc[cb][r];
+          for (int r = 0; r < 4; ++r) {
+            if (rmask[h] & (1 << r)) {
+#pragma unroll
+              for (int cb = 0; cb < CB; ++cb) xr[2 * r * P + 16 * cb] = acc[h][cb][r];
+            }
           }
         }
         __syncthreads();
       } else {
         float* R = reinterpret_cast<float*>(fb);
-        const int wave = threadIdx.x / 64;
+        const int rb0 = 2 * (threadIdx.x / 64);
         __syncthreads();
-        if (mf) {
 #pragma unroll
-          for (int cb = 0; cb < 2; ++cb)
+        for (int h = 0; h < 2; ++h) {
+          if (h < nrb) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              R[(16 * wave + 4 * (lane / 16) + r) * ax->r_pitch + 16 * cb + lane % 16] = acc[cb][r];
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                R[(16 * (rb0 + h) + 4 * (lane / 16) + r) * ax->r_pitch + 16 * cb + lane % 16] =
+                    acc[h][cb][r];
+          }
         }
         __syncthreads();
         mf_unfold<float, W>(R, *ax, n, x, P);
@@ -317,6 +356,7 @@ struct MfmaXfF32 {
 // ------------------------------------------------------------------ FP64
 struct MfmaXfF64 {
   static constexpr int W = 16;
+  static constexpr int THREADS = MF_THREADS;
   const Geom* g;
   const MfmaAxisDev* ax;
   double* fb;
@@ -377,18 +417,24 @@ struct MfmaXfF64 {
   }
 };
 
+// Engines per field type: the x axis (tiles of every species) and the
+// strided axes.
 template <typename T>
-struct MfmaXfSel;
+struct XfSel;
 template <>
-struct MfmaXfSel<float> {
-  using type = MfmaXfF32;
+struct XfSel<float> {
+  using X = MfmaXfF32<16>;
+  using Z = MfmaXfF32<32>;
 };
 template <>
-struct MfmaXfSel<double> {
-  using type = MfmaXfF64;
+struct XfSel<double> {
+  using X = MfmaXfF64;
+  using Z = MfmaXfF64;
 };
 template <typename T>
-using MfmaXf = typename MfmaXfSel<T>::type;
+using XfX = typename XfSel<T>::X;
+template <typename T>
+using XfZ = typename XfSel<T>::Z;
 
 // ------------------------------------------------------------------ kernels
 // Persistent: block b handles tiles b, b + gridDim.x, ... The global loads of
@@ -401,72 +447,72 @@ struct MfPrefetch {
 };
 template <>
 struct MfPrefetch<float> {
-  static constexpr int fwd = 4;
+  static constexpr int fwd = 0;
 };
 
-template <typename T>
-__global__ __launch_bounds__(MF_THREADS) void k_xstage_m(StageArgs<T> a, MfmaAxisDev ax) {
+template <typename T, class XF>
+__global__ __launch_bounds__(XF::THREADS, 4) void k_xstage_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
+  XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   TilePrefetch<T, MfPrefetch<T>::fwd> pf;
-  pf.issue(a.g, blockIdx.x, a.P, a.S);
+  pf.issue(a.g, blockIdx.x, a.P, a.g.spt);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pf.commit(a.g, tile, a.P, buf, a.S);
+    pf.commit(a.g, tile, a.P, buf, a.g.spt);
     __syncthreads();
-    pf.issue(a.g, tile + gridDim.x, a.P, a.S);
+    pf.issue(a.g, tile + gridDim.x, a.P, a.g.spt);
     run_x(a, buf, tile, xf);
     __syncthreads();
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(MF_THREADS) void k_zstage_m(StageArgs<T> a, MfmaAxisDev ax) {
+template <typename T, class XF>
+__global__ __launch_bounds__(XF::THREADS, 4) void k_zstage_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
+  XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const T* src = a.src ? a.src : a.P;
   TilePrefetch<T, MfPrefetch<T>::fwd> pf;
-  pf.issue(a.g, blockIdx.x, src, a.S);
+  pf.issue(a.g, blockIdx.x, src, a.g.spt);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pf.commit(a.g, tile, src, buf, a.S);
+    pf.commit(a.g, tile, src, buf, a.g.spt);
     __syncthreads();
-    pf.issue(a.g, tile + gridDim.x, src, a.S);
+    pf.issue(a.g, tile + gridDim.x, src, a.g.spt);
     run_z(a, buf, tile, xf);
     __syncthreads();
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(MF_THREADS) void k_xadj_m(StageArgs<T> a, MfmaAxisDev ax) {
+template <typename T, class XF>
+__global__ __launch_bounds__(XF::THREADS, 4) void k_xadj_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
+  XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   double pacc[MAX_PARAMS];
   for (int k = 0; k < MAX_PARAMS; ++k) pacc[k] = 0.0;
   TilePrefetch<T, MfPrefetch<T>::fwd> pf;
-  pf.issue(a.g, blockIdx.x, a.P, a.S);
+  pf.issue(a.g, blockIdx.x, a.P, a.g.spt);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pf.commit(a.g, tile, a.P, buf, a.S);
+    pf.commit(a.g, tile, a.P, buf, a.g.spt);
     __syncthreads();
-    pf.issue(a.g, tile + gridDim.x, a.P, a.S);
+    pf.issue(a.g, tile + gridDim.x, a.P, a.g.spt);
     run_xadj(a, buf, tile, xf, pacc);
     __syncthreads();
   }
   if (a.rp_acc) block_add_partials(reinterpret_cast<double*>(smem_raw), pacc, a.rxn.np, a.rp_acc);
 }
 
-template <typename T>
-__global__ __launch_bounds__(MF_THREADS) void k_zadj_m(StageArgs<T> a, MfmaAxisDev ax) {
+template <typename T, class XF>
+__global__ __launch_bounds__(XF::THREADS, 4) void k_zadj_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
+  XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   TilePrefetch<T, 0> pf;
-  pf.issue(a.g, blockIdx.x, a.P, a.S);
+  pf.issue(a.g, blockIdx.x, a.P, a.g.spt);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pf.commit(a.g, tile, a.P, buf, a.S);
+    pf.commit(a.g, tile, a.P, buf, a.g.spt);
     __syncthreads();
-    pf.issue(a.g, tile + gridDim.x, a.P, a.S);
+    pf.issue(a.g, tile + gridDim.x, a.P, a.g.spt);
     run_zadj(a, buf, tile, xf);
     __syncthreads();
   }
@@ -474,19 +520,19 @@ __global__ __launch_bounds__(MF_THREADS) void k_zadj_m(StageArgs<T> a, MfmaAxisD
 
 // One transform along one axis, src -> dst (may alias), optional Neumann
 // point weights before (divide) or after (multiply).
-template <typename T>
-__global__ __launch_bounds__(MF_THREADS) void k_single_m(SingleArgs<T> a, MfmaAxisDev ax) {
+template <typename T, class XF>
+__global__ __launch_bounds__(XF::THREADS, 4) void k_single_m(SingleArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  MfmaXf<T> xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
+  XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const Geom& g = a.g;
   const int ne = g.n * g.W;
   TilePrefetch<T, MfPrefetch<T>::fwd> pf;
-  pf.issue(g, blockIdx.x, a.src, a.S);
+  pf.issue(g, blockIdx.x, a.src, g.spt);
   for (long long tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
-    pf.commit(g, tile, a.src, buf, a.S);
+    pf.commit(g, tile, a.src, buf, g.spt);
     __syncthreads();
-    pf.issue(g, tile + gridDim.x, a.src, a.S);
+    pf.issue(g, tile + gridDim.x, a.src, g.spt);
     const TileRef tr = tile_ref(g, tile);
     if (a.pre_divide_w) {
       for (int e = threadIdx.x; e < ne; e += blockDim.x) {
@@ -495,11 +541,11 @@ __global__ __launch_bounds__(MF_THREADS) void k_single_m(SingleArgs<T> a, MfmaAx
         long long idx;
         if (!elem(g, tr, j, w, idx)) continue;
         const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
-        for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] /= wt;
+        for (int s = 0; s < g.spt; ++s) buf[(s * g.n + j) * g.pitch + w] /= wt;
       }
       __syncthreads();
     }
-    xf(buf, a.S);
+    xf(buf, g.spt);
     if (a.post_multiply_w) {
       for (int e = threadIdx.x; e < ne; e += blockDim.x) {
         int j, w;
@@ -507,11 +553,11 @@ __global__ __launch_bounds__(MF_THREADS) void k_single_m(SingleArgs<T> a, MfmaAx
         long long idx;
         if (!elem(g, tr, j, w, idx)) continue;
         const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
-        for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] *= wt;
+        for (int s = 0; s < g.spt; ++s) buf[(s * g.n + j) * g.pitch + w] *= wt;
       }
       __syncthreads();
     }
-    store_tile_fast(g, tile, buf, a.dst, a.S);
+    store_tile_fast(g, tile, buf, a.dst, g.spt);
     __syncthreads();
   }
 }

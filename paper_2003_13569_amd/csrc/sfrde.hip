@@ -221,6 +221,7 @@ void make_geom(sfrde_plan_s* p, int axis) {
   long long inner = 1;
   for (int a = 0; a < axis; ++a) inner *= p->n[a];
   g.n = (int)n;
+  g.spt = p->S;
   g.inner = inner;
   g.total = p->total;
   // Tile width: a power of two with n*W <= KMAX*NTHREADS, the tile of all
@@ -349,7 +350,9 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   if (env && strcmp(env, "dense") == 0) return SFRDE_OK;
   MfmaTables t = mfma_tables(p->bc, p->n[axis]);
   if (!t.ok) return SFRDE_OK;
-  const int W = p->dtype == SFRDE_F32 ? MfmaXfF32::W : MfmaXfF64::W;
+  const bool f32 = p->dtype == SFRDE_F32;
+  const int W = f32 ? (axis == 0 ? XfX<float>::W : XfZ<float>::W) : MfmaXfF64::W;
+  const int threads = f32 ? XfZ<float>::THREADS : MfmaXfF64::THREADS;
   // geometry
   Geom& g = p->geom_m[axis];
   g = p->geom[axis];
@@ -361,6 +364,12 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
     g.tpo = 1;
     g.ntiles = (g.outer + W - 1) / W;
   } else {
+    // FP32 tiles along strided axes hold one species: the species index
+    // becomes part of the outer block index (the fields are [S][total]).
+    if (f32) {
+      g.outer *= p->S;
+      g.spt = 1;
+    }
     g.tpo = (g.inner + W - 1) / W;
     g.ntiles = g.outer * g.tpo;
   }
@@ -371,7 +380,7 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   ax.fb_pitch = p->dtype == SFRDE_F32 ? F32_FBP : t.hK + 2;
   ax.r_pitch = W + 1;
   ax.direct = p->bc != SFRDE_BC_PERIODIC;
-  size_t tile_bytes = (size_t)p->S * g.n * g.pitch * p->w;
+  size_t tile_bytes = (size_t)g.spt * g.n * g.pitch * p->w;
   tile_bytes = (tile_bytes + 15) / 16 * 16;
   // fold area: FP32 plans keep two binary16 terms of s and d and the column
   // scales; FP64 plans s and d.
@@ -380,10 +389,13 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   const size_t res_bytes = (size_t)16 * t.RB * ax.r_pitch * p->w;
   ax.fb_off = (int)tile_bytes;
   size_t lds = tile_bytes + std::max(fold_bytes, res_bytes);
-  lds = std::max<size_t>(lds, (size_t)MF_THREADS * sizeof(double));
+  lds = std::max<size_t>(lds, (size_t)threads * sizeof(double));
   if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: keep the dense kernels
   p->lds_m[axis] = lds;
-  p->grid_m[axis] = (unsigned)std::min<long long>(g.ntiles, (long long)p->n_cu);
+  // persistent grid: as many blocks as fit on the CUs at once
+  const long long per_cu = std::max<long long>(
+      1, std::min<long long>((long long)(160 * 1024 / lds), MF_THREADS / threads));
+  p->grid_m[axis] = (unsigned)std::min<long long>(g.ntiles, (long long)p->n_cu * per_cu);
   // fragment-ordered split matrices
   if (p->dtype == SFRDE_F32) {
     std::vector<unsigned short> frag((size_t)MF_WAVES * MF_KSMAX_F32 * 2 * 64 * 8, 0);
@@ -421,11 +433,12 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
 
 template <typename T>
 int set_lds_attrs(size_t bytes) {
-  const void* fns[] = {reinterpret_cast<const void*>(&k_xstage_m<T>),
-                       reinterpret_cast<const void*>(&k_zstage_m<T>),
-                       reinterpret_cast<const void*>(&k_xadj_m<T>),
-                       reinterpret_cast<const void*>(&k_zadj_m<T>),
-                       reinterpret_cast<const void*>(&k_single_m<T>)};
+  const void* fns[] = {reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>>),
+                       reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>>),
+                       reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>>),
+                       reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>>),
+                       reinterpret_cast<const void*>(&k_single_m<T, XfX<T>>),
+                       reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>>)};
   for (const void* f : fns)
     HIPCHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   return SFRDE_OK;
@@ -475,8 +488,12 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
   a.n2 = p->n[2];
   const long long pk = prof_start(p, KC_Y);
   if (p->use_m[axis])
-    hipLaunchKernelGGL(k_single_m<T>, dim3(p->grid_m[axis]), dim3(MF_THREADS), p->lds_m[axis],
-                       p->stream, a, p->mfax[axis]);
+    if (axis == 0)
+      hipLaunchKernelGGL((k_single_m<T, XfX<T>>), dim3(p->grid_m[axis]), dim3(XfX<T>::THREADS),
+                         p->lds_m[axis], p->stream, a, p->mfax[axis]);
+    else
+      hipLaunchKernelGGL((k_single_m<T, XfZ<T>>), dim3(p->grid_m[axis]), dim3(XfZ<T>::THREADS),
+                         p->lds_m[axis], p->stream, a, p->mfax[axis]);
   else
     hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[axis],
                        p->stream, a);
@@ -513,7 +530,7 @@ int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
   a.st_phys = st_phys;
   const long long pk = prof_start(p, KC_X);
   if (p->use_m[0])
-    hipLaunchKernelGGL(k_xstage_m<T>, dim3(p->grid_m[0]), dim3(MF_THREADS),
+    hipLaunchKernelGGL((k_xstage_m<T, XfX<T>>), dim3(p->grid_m[0]), dim3(XfX<T>::THREADS),
                        p->lds_m[0], p->stream, a, p->mfax[0]);
   else
     hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
@@ -533,7 +550,7 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat)
   a.st_fhat = st_fhat;
   const long long pk = prof_start(p, KC_Z);
   if (p->use_m[ax])
-    hipLaunchKernelGGL(k_zstage_m<T>, dim3(p->grid_m[ax]), dim3(MF_THREADS),
+    hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>>), dim3(p->grid_m[ax]), dim3(XfZ<T>::THREADS),
                        p->lds_m[ax], p->stream, a, p->mfax[ax]);
   else
     hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
@@ -661,7 +678,7 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
   a.rp_acc = p->rp_acc;
   const long long pk = prof_start(p, KC_XADJ);
   if (p->use_m[0])
-    hipLaunchKernelGGL(k_xadj_m<T>, dim3(p->grid_m[0]), dim3(MF_THREADS),
+    hipLaunchKernelGGL((k_xadj_m<T, XfX<T>>), dim3(p->grid_m[0]), dim3(XfX<T>::THREADS),
                        p->lds_m[0], p->stream, a, p->mfax[0]);
   else
     hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
@@ -685,7 +702,7 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
   if (!p->G) a.dcoef = nullptr;
   const long long pk = prof_start(p, KC_ZADJ);
   if (p->use_m[ax])
-    hipLaunchKernelGGL(k_zadj_m<T>, dim3(p->grid_m[ax]), dim3(MF_THREADS),
+    hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>>), dim3(p->grid_m[ax]), dim3(XfZ<T>::THREADS),
                        p->lds_m[ax], p->stream, a, p->mfax[ax]);
   else
     hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
