@@ -39,6 +39,7 @@ struct Geom {
   int n;            // length of the transformed axis
   int spt;          // species per tile: all, or 1 (strided axes may split tiles by species,
                     // with the species index folded into the outer blocks)
+  int fast;         // full tiles may use the 32-bit-offset vector paths of the FP32 engine
   int W;            // lines per tile (a power of two)
   int pitch;        // LDS row pitch (>= W)
   int wshift;       // log2(W)

@@ -22,6 +22,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace sfrde {
@@ -160,6 +162,7 @@ template <int W_>
 struct MfmaXfF32 {
   static constexpr int W = W_;
   static constexpr int THREADS = 512;
+  static constexpr int MIN_WAVES_PER_EU = 2;  // one block per CU, 256 registers per lane
   static constexpr int P = W + 1;             // LDS row pitch of the tile
   static constexpr int FBP = F32_FBP;
   static constexpr int TS = 2 * W * F32_FBP;  // binary16 elements between the two terms
@@ -215,6 +218,10 @@ struct MfmaXfF32 {
         if (h < nrb && row0 + 2 * r < n) rmask[h] |= 1 << r;
     }
     shareB = nrb < 2 || isO[0] == isO[1];
+    // Wait for the fragment loads here: left pending, they would make the
+    // compiler wait for every outstanding load before the first product of
+    // each tile, prefetches included. (gfx9 s_waitcnt: vmcnt 0, others max.)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     // fold item; entries past the folded length come out as zeros
     col = (threadIdx.x >> 4) & (W - 1);
     i0 = (threadIdx.x & 15) << 3;
@@ -357,6 +364,7 @@ struct MfmaXfF32 {
 struct MfmaXfF64 {
   static constexpr int W = 16;
   static constexpr int THREADS = MF_THREADS;
+  static constexpr int MIN_WAVES_PER_EU = 4;
   const Geom* g;
   const MfmaAxisDev* ax;
   double* fb;
@@ -436,103 +444,457 @@ using XfX = typename XfSel<T>::X;
 template <typename T>
 using XfZ = typename XfSel<T>::Z;
 
-// ------------------------------------------------------------------ kernels
-// Persistent: block b handles tiles b, b + gridDim.x, ... The global loads of
-// the next tile are issued before the current tile is computed.
-// Prefetch depth (16-byte vectors per thread) where the registers allow it:
-// the FP32 forward, single-axis and adjoint-X kernels; 0 loads in place.
-template <typename T>
-struct MfPrefetch {
-  static constexpr int fwd = 0;
-};
-template <>
-struct MfPrefetch<float> {
-  static constexpr int fwd = 0;
+// ------------------------------------------------------------------ tile movement
+// FP32 engine tiles move in 16-byte vectors with per-thread offsets from the
+// tile base (full tiles, 16-byte aligned fields, the shapes below); other
+// tiles use the generic paths of kernels.h.
+//
+// Strided axis (W = 32, one species per tile, n a multiple of 64 up to 256):
+// thread t moves rows t/8 + 64k, lanes 4(t%8) .. +3.
+// x axis (W = 16 lines, every species, n in {64, 128, 256}, 128 <= S n <= 512): a wave moves
+// 16 consecutive vectors of each of 4 lines, so that the four scalar LDS
+// writes of a vector land in distinct banks across the wave.
+template <typename T, int W>
+struct TileIO {
+  __device__ __forceinline__ static void issue(const Geom&, const TileRef&, const T*, float4*) {}
+  __device__ __forceinline__ static void commit(const Geom&, const float4*, T*) {}
+  __device__ __forceinline__ static void store(const Geom&, const TileRef&, const T*, T*) {}
 };
 
-template <typename T, class XF>
-__global__ __launch_bounds__(XF::THREADS, 4) void k_xstage_m(StageArgs<T> a, MfmaAxisDev ax) {
+template <>
+struct TileIO<float, 32> {
+  static constexpr int P = 33, VPR = 8, RSTEP = 512 / VPR, MAXK = 4;
+  __device__ __forceinline__ static int row0() { return threadIdx.x / VPR; }
+  __device__ __forceinline__ static int lane4() { return (threadIdx.x % VPR) * 4; }
+  __device__ __forceinline__ static void issue(const Geom& g, const TileRef& tr, const float* src,
+                                               float4* v) {
+    const int r0 = row0(), w4 = lane4();
+    const long long inner = g.inner;
+    const float* sp = src + tr.base + r0 * inner + w4;
+    // straight-line loads (rows past n repeat row block 0), so that the
+    // compiler's wait counts stay exact
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k)
+      v[k] = *reinterpret_cast<const float4*>(sp + (64 * k < g.n ? k : 0) * RSTEP * inner);
+  }
+  __device__ __forceinline__ static void commit(const Geom& g, const float4* v, float* buf) {
+    const int r0 = row0(), w4 = lane4();
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k)
+      if (64 * k < g.n) {
+        float* b = buf + (r0 + RSTEP * k) * P + w4;
+        b[0] = v[k].x;
+        b[1] = v[k].y;
+        b[2] = v[k].z;
+        b[3] = v[k].w;
+      }
+  }
+  __device__ __forceinline__ static void store(const Geom& g, const TileRef& tr, const float* buf,
+                                               float* dst) {
+    const int r0 = row0(), w4 = lane4();
+    const long long inner = g.inner;
+    float* dp = dst + tr.base + r0 * inner + w4;
+#pragma unroll
+    for (int k = 0; k < MAXK; ++k)
+      if (64 * k < g.n) {
+        const float* b = buf + (r0 + RSTEP * k) * P + w4;
+        *reinterpret_cast<float4*>(dp + k * RSTEP * inner) = make_float4(b[0], b[1], b[2], b[3]);
+      }
+  }
+};
+
+template <>
+struct TileIO<float, 16> {
+  static constexpr int P = 17, MAXV = 4;  // vectors per thread: S * 16 * n / 4 / 512 <= 4
+  // vector v of species s -> offset within the species' field from the tile
+  // base, and LDS offset
+  __device__ __forceinline__ static int log2n64(const Geom& g) {
+    return g.n == 256 ? 2 : (g.n == 128 ? 1 : 0);
+  }
+  __device__ __forceinline__ static void coords(const Geom& g, int s, int v, int& go, int& lo) {
+    const int lg = log2n64(g);
+    const int c16 = v & 15, l4 = (v >> 4) & 3, rest = v >> 6;
+    const int line = 4 * (rest >> lg) + l4;
+    const int j = 4 * (16 * (rest & ((1 << lg) - 1)) + c16);
+    go = line * g.n + j;
+    lo = (s * g.n + j) * P + line;
+  }
+  __device__ __forceinline__ static void issue(const Geom& g, const TileRef& tr, const float* src,
+                                               float4* v) {
+    const int sh = log2n64(g) + 8;  // log2 of the vectors per species, 4n
+    const int nv = g.spt << sh;  // vectors in the tile, a multiple of 512
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      // straight-line loads (vectors past the tile repeat the first block)
+      const int q = threadIdx.x + (512 * k < nv ? 512 * k : 0), s = q >> sh;
+      int go, lo;
+      coords(g, s, q & ((1 << sh) - 1), go, lo);
+      v[k] = *reinterpret_cast<const float4*>(src + s * g.total + tr.base + go);
+    }
+  }
+  __device__ __forceinline__ static void commit(const Geom& g, const float4* v, float* buf) {
+    const int sh = log2n64(g) + 8;
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      const int q = threadIdx.x + 512 * k, s = q >> sh;
+      if (s < g.spt) {
+        int go, lo;
+        coords(g, s, q & ((1 << sh) - 1), go, lo);
+        float* b = buf + lo;
+        b[0] = v[k].x;
+        b[P] = v[k].y;
+        b[2 * P] = v[k].z;
+        b[3 * P] = v[k].w;
+      }
+    }
+  }
+  __device__ __forceinline__ static void store(const Geom& g, const TileRef& tr, const float* buf,
+                                               float* dst) {
+    const int sh = log2n64(g) + 8;
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      const int q = threadIdx.x + 512 * k, s = q >> sh;
+      if (s < g.spt) {
+        int go, lo;
+        coords(g, s, q & ((1 << sh) - 1), go, lo);
+        const float* b = buf + lo;
+        *reinterpret_cast<float4*>(dst + s * g.total + tr.base + go) =
+            make_float4(b[0], b[P], b[2 * P], b[3 * P]);
+      }
+    }
+  }
+};
+
+// Register prefetch of a tile. FAST kernels (chosen by the host when every
+// tile is full, the shapes fit the layouts above and the pointers are
+// 16-byte aligned) move tiles with TileIO only; the others with the generic
+// paths, loading in place. Keeping the two apart keeps the compiler's wait
+// counts exact on the fast path.
+template <typename T, int W, bool FAST>
+struct TilePipe {
+  float4 v[4];
+  __device__ __forceinline__ void issue(const Geom& g, long long tile, const T* src) {
+    if (FAST && tile < g.ntiles) TileIO<T, W>::issue(g, tile_ref(g, tile), src, v);
+  }
+  __device__ __forceinline__ void commit(const Geom& g, long long tile, const T* src, T* buf) {
+    if (FAST)
+      TileIO<T, W>::commit(g, v, buf);
+    else
+      load_tile_fast(g, tile, src, buf, g.spt);
+  }
+};
+
+template <typename T, int W, bool FAST>
+__device__ __forceinline__ void tile_store(const Geom& g, long long tile, const T* buf, T* dst) {
+  if (FAST)
+    TileIO<T, W>::store(g, tile_ref(g, tile), buf, dst);
+  else
+    store_tile_fast(g, tile, buf, dst, g.spt);
+}
+
+// Arrays a forward stage reads for one strided FP32 tile (L-table plans),
+// loaded ahead of the forward transform in the thread layout of
+// TileIO<float, 32>: L, then r1, r2 =
+//   stage 0: u_hat, -;  stage 1: u_hat, acc;  stage 2: acc, c_tilde;  stage 3: acc, -.
+template <int MODE>
+struct StageLoads {
+  float4 L[4], r1[4], r2[4];
+  __device__ __forceinline__ void issue(const StageArgs<float>& a, const TileRef& tr) {
+    using IO = TileIO<float, 32>;
+    const long long inner = a.g.inner;
+    const long long i0 = tr.base + IO::row0() * inner + IO::lane4();
+    const float* p1 = MODE <= 1 ? a.uhat : a.acc;
+    const float* p2 = MODE == 1 ? a.acc : a.ctil;
+#pragma unroll
+    for (int k = 0; k < IO::MAXK; ++k) {
+      const long long i = i0 + (64 * k < a.g.n ? k : 0) * IO::RSTEP * inner;
+      L[k] = *reinterpret_cast<const float4*>(a.ltab + i);
+      r1[k] = *reinterpret_cast<const float4*>(p1 + i);
+      if (MODE == 1 || MODE == 2) r2[k] = *reinterpret_cast<const float4*>(p2 + i);
+    }
+  }
+};
+
+// Stage combine from preloaded arrays (same arithmetic as combine_vec).
+template <int MODE>
+__device__ __forceinline__ void combine_pre(const StageArgs<float>& a, float* buf,
+                                            const TileRef& tr, const StageLoads<MODE>& ld) {
+  using IO = TileIO<float, 32>;
+  const Geom& g = a.g;
+  const long long cst = (long long)a.S * g.total;
+  const int r0 = IO::row0(), w4 = IO::lane4();
+  const long long inner = g.inner;
+  const long long i0 = tr.base + r0 * inner + w4;
+  const float cs = a.cs, tau = a.tau;
+#pragma unroll
+  for (int k = 0; k < IO::MAXK; ++k) {
+    if (64 * k >= g.n) break;
+    const long long i = i0 + k * IO::RSTEP * inner;
+    float* cell = buf + (r0 + IO::RSTEP * k) * IO::P + w4;
+    const float4 fh = make_float4(cell[0], cell[1], cell[2], cell[3]);
+    float4 o0, o1, out;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+      stage_coefs_L<float>(MODE, vget<float>(ld.L[k], e), tau, c0, c1, c2, c3);
+      const float f = vget<float>(fh, e);
+      const float x1 = vget<float>(ld.r1[k], e);
+      if (MODE == 0) {
+        const float av = c0 * x1 + c1 * f;
+        vset<float>(o0, e, c0 * av - c1 * f);
+        vset<float>(o1, e, c2 * x1 + c3 * f);
+        vset<float>(out, e, cs * av);
+      } else if (MODE == 1) {
+        vset<float>(out, e, cs * (c0 * x1 + c1 * f));
+        vset<float>(o1, e, vget<float>(ld.r2[k], e) + c2 * f);
+      } else if (MODE == 2) {
+        vset<float>(out, e, cs * (vget<float>(ld.r2[k], e) + 2.f * c1 * f));
+        vset<float>(o1, e, x1 + c2 * f);
+      } else {
+        const float un = x1 + c2 * f;
+        vset<float>(o0, e, un);
+        vset<float>(out, e, cs * un);
+      }
+    }
+    if (MODE == 0) {
+      if (a.st_uhat) *reinterpret_cast<float4*>(a.st_uhat + i) = ld.r1[k];
+      *reinterpret_cast<float4*>(a.ctil + i) = o0;
+    }
+    if (a.st_fhat) *reinterpret_cast<float4*>(a.st_fhat + MODE * cst + i) = fh;
+    if (MODE <= 2) *reinterpret_cast<float4*>(a.acc + i) = o1;
+    if (MODE == 3) *reinterpret_cast<float4*>(a.uhat + i) = o0;
+    cell[0] = out.x;
+    cell[1] = out.y;
+    cell[2] = out.z;
+    cell[3] = out.w;
+  }
+}
+
+// Forward stage combine on a one-species strided FP32 tile, in the thread
+// layout of TileIO<float, 32> (same arithmetic as combine_vec).
+template <int MODE, bool LT>
+__device__ __forceinline__ void combine_tile32(const StageArgs<float>& a, float* buf,
+                                               const TileRef& tr) {
+  using IO = TileIO<float, 32>;
+  const Geom& g = a.g;
+  const long long cst = (long long)a.S * g.total;
+  const int r0 = IO::row0(), w4 = IO::lane4();
+  const long long inner = g.inner;
+  const long long i0 = tr.base + r0 * inner + w4;
+  const float cs = a.cs, tau = a.tau;
+#pragma unroll 1
+  for (int k = 0; k < IO::MAXK; ++k) {
+    if (64 * k >= g.n) break;
+    const long long i = i0 + k * IO::RSTEP * inner;
+    float* cell = buf + (r0 + IO::RSTEP * k) * IO::P + w4;
+    float4 Lv, t0, t1, t2, t3, uh, ac, ct;
+    if (LT) {
+      Lv = *reinterpret_cast<const float4*>(a.ltab + i);
+    } else {
+      const float* cf = a.coef + i;
+      if (MODE <= 1) t0 = *reinterpret_cast<const float4*>(cf + C_Q * cst);
+      if (MODE <= 2) t1 = *reinterpret_cast<const float4*>(cf + C_PHI * cst);
+      t2 = *reinterpret_cast<const float4*>(
+          cf + (MODE == 0 ? C_R : MODE == 3 ? C_PHI3 : C_PHI2) * cst);
+      if (MODE == 0) t3 = *reinterpret_cast<const float4*>(cf + C_PHI1 * cst);
+    }
+    if (MODE <= 1) uh = *reinterpret_cast<const float4*>(a.uhat + i);
+    if (MODE >= 1) ac = *reinterpret_cast<const float4*>(a.acc + i);
+    if (MODE == 2) ct = *reinterpret_cast<const float4*>(a.ctil + i);
+    float4 fh = make_float4(cell[0], cell[1], cell[2], cell[3]);
+    float4 o0, o1, out;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
+      if (LT) {
+        stage_coefs_L<float>(MODE, vget<float>(Lv, e), tau, c0, c1, c2, c3);
+      } else {
+        if (MODE <= 1) c0 = vget<float>(t0, e);
+        if (MODE <= 2) c1 = vget<float>(t1, e);
+        c2 = vget<float>(t2, e);
+        if (MODE == 0) c3 = vget<float>(t3, e);
+      }
+      const float f = vget<float>(fh, e);
+      if (MODE == 0) {
+        const float u = vget<float>(uh, e);
+        const float av = c0 * u + c1 * f;
+        vset<float>(o0, e, c0 * av - c1 * f);
+        vset<float>(o1, e, c2 * u + c3 * f);
+        vset<float>(out, e, cs * av);
+      } else if (MODE == 1) {
+        vset<float>(out, e, cs * (c0 * vget<float>(uh, e) + c1 * f));
+        vset<float>(o1, e, vget<float>(ac, e) + c2 * f);
+      } else if (MODE == 2) {
+        vset<float>(out, e, cs * (vget<float>(ct, e) + 2.f * c1 * f));
+        vset<float>(o1, e, vget<float>(ac, e) + c2 * f);
+      } else {
+        const float un = vget<float>(ac, e) + c2 * f;
+        vset<float>(o0, e, un);
+        vset<float>(out, e, cs * un);
+      }
+    }
+    if (MODE == 0) {
+      if (a.st_uhat) *reinterpret_cast<float4*>(a.st_uhat + i) = uh;
+      *reinterpret_cast<float4*>(a.ctil + i) = o0;
+    }
+    if (a.st_fhat) *reinterpret_cast<float4*>(a.st_fhat + MODE * cst + i) = fh;
+    if (MODE <= 2) *reinterpret_cast<float4*>(a.acc + i) = o1;
+    if (MODE == 3) *reinterpret_cast<float4*>(a.uhat + i) = o0;
+    cell[0] = out.x;
+    cell[1] = out.y;
+    cell[2] = out.z;
+    cell[3] = out.w;
+  }
+}
+
+template <typename T, int W, bool FAST>
+__device__ __forceinline__ void combine_tile(const StageArgs<T>& a, T* buf, long long tile) {
+  if constexpr (FAST && std::is_same<T, float>::value && W == 32) {
+    const TileRef tr = tile_ref(a.g, tile);
+    if (a.mode <= 3 && a.g.spt == 1) {
+      const bool lt = a.ltab != nullptr;
+      switch (a.mode) {
+        case 0:
+          lt ? combine_tile32<0, true>(a, buf, tr) : combine_tile32<0, false>(a, buf, tr);
+          return;
+        case 1:
+          lt ? combine_tile32<1, true>(a, buf, tr) : combine_tile32<1, false>(a, buf, tr);
+          return;
+        case 2:
+          lt ? combine_tile32<2, true>(a, buf, tr) : combine_tile32<2, false>(a, buf, tr);
+          return;
+        default:
+          lt ? combine_tile32<3, true>(a, buf, tr) : combine_tile32<3, false>(a, buf, tr);
+          return;
+      }
+    }
+  }
+  pw_combine_fast(a, buf, tile);
+}
+
+// ------------------------------------------------------------------ kernels
+// Persistent: block b handles tiles b, b + gridDim.x, ... The loads of the
+// next tile are issued before the current one is computed (where they do not
+// compete with other loads of the current tile), and the Z kernels' stage
+// arrays before the forward transform.
+template <typename T, class XF, bool FAST>
+__global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
-  TilePrefetch<T, MfPrefetch<T>::fwd> pf;
-  pf.issue(a.g, blockIdx.x, a.P, a.g.spt);
+  const int S = a.g.spt;
+  TilePipe<T, XF::W, FAST> pipe;
+  pipe.issue(a.g, blockIdx.x, a.P);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pf.commit(a.g, tile, a.P, buf, a.g.spt);
+    pipe.commit(a.g, tile, a.P, buf);
     __syncthreads();
-    pf.issue(a.g, tile + gridDim.x, a.P, a.g.spt);
-    run_x(a, buf, tile, xf);
+    pipe.issue(a.g, tile + gridDim.x, a.P);
+    xf(buf, S);
+    if (pw_reaction(a, buf, tile)) a.flag[0] = 1;
+    __syncthreads();
+    xf(buf, S);
+    tile_store<T, XF::W, FAST>(a.g, tile, buf, a.P);
     __syncthreads();
   }
 }
 
-template <typename T, class XF>
-__global__ __launch_bounds__(XF::THREADS, 4) void k_zstage_m(StageArgs<T> a, MfmaAxisDev ax) {
+// MODE >= 0: the stage is known at compile time and FAST L-table FP32 plans
+// load the stage arrays ahead; MODE < 0 takes a.mode at run time.
+template <typename T, class XF, int MODE, bool FAST>
+__global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const T* src = a.src ? a.src : a.P;
-  TilePrefetch<T, MfPrefetch<T>::fwd> pf;
-  pf.issue(a.g, blockIdx.x, src, a.g.spt);
+  const int S = a.g.spt;
+  constexpr bool PRE = FAST && MODE >= 0 && std::is_same<T, float>::value && XF::W == 32;
+  TilePipe<T, XF::W, FAST> pipe;
+  pipe.issue(a.g, blockIdx.x, src);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pf.commit(a.g, tile, src, buf, a.g.spt);
+    pipe.commit(a.g, tile, src, buf);
     __syncthreads();
-    pf.issue(a.g, tile + gridDim.x, src, a.g.spt);
-    run_z(a, buf, tile, xf);
+    if constexpr (PRE) {
+      const TileRef tr = tile_ref(a.g, tile);
+      const bool pre = a.ltab && S == 1 && !a.src;
+      StageLoads<(PRE ? MODE : 0)> ld;
+      if (pre) ld.issue(a, tr);
+      xf(buf, S);
+      if (pre)
+        combine_pre(a, buf, tr, ld);
+      else
+        combine_tile<T, XF::W, FAST>(a, buf, tile);
+    } else {
+      if (!a.src) xf(buf, S);
+      combine_tile<T, XF::W, FAST>(a, buf, tile);
+    }
+    __syncthreads();
+    pipe.issue(a.g, tile + gridDim.x, src);
+    xf(buf, S);
+    tile_store<T, XF::W, FAST>(a.g, tile, buf, a.P);
     __syncthreads();
   }
 }
 
-template <typename T, class XF>
-__global__ __launch_bounds__(XF::THREADS, 4) void k_xadj_m(StageArgs<T> a, MfmaAxisDev ax) {
+template <typename T, class XF, bool FAST>
+__global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   double pacc[MAX_PARAMS];
   for (int k = 0; k < MAX_PARAMS; ++k) pacc[k] = 0.0;
-  TilePrefetch<T, MfPrefetch<T>::fwd> pf;
-  pf.issue(a.g, blockIdx.x, a.P, a.g.spt);
+  const int S = a.g.spt;
+  TilePipe<T, XF::W, FAST> pipe;
+  pipe.issue(a.g, blockIdx.x, a.P);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pf.commit(a.g, tile, a.P, buf, a.g.spt);
+    pipe.commit(a.g, tile, a.P, buf);
     __syncthreads();
-    pf.issue(a.g, tile + gridDim.x, a.P, a.g.spt);
-    run_xadj(a, buf, tile, xf, pacc);
+    xf(buf, S);
+    pw_adj_reaction(a, buf, tile, pacc);
+    __syncthreads();
+    pipe.issue(a.g, tile + gridDim.x, a.P);
+    xf(buf, S);
+    tile_store<T, XF::W, FAST>(a.g, tile, buf, a.P);
     __syncthreads();
   }
   if (a.rp_acc) block_add_partials(reinterpret_cast<double*>(smem_raw), pacc, a.rxn.np, a.rp_acc);
 }
 
-template <typename T, class XF>
-__global__ __launch_bounds__(XF::THREADS, 4) void k_zadj_m(StageArgs<T> a, MfmaAxisDev ax) {
+template <typename T, class XF, bool FAST>
+__global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
-  TilePrefetch<T, 0> pf;
-  pf.issue(a.g, blockIdx.x, a.P, a.g.spt);
+  const int S = a.g.spt;
+  TilePipe<T, XF::W, FAST> pipe;
+  pipe.issue(a.g, blockIdx.x, a.P);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pf.commit(a.g, tile, a.P, buf, a.g.spt);
+    pipe.commit(a.g, tile, a.P, buf);
     __syncthreads();
-    pf.issue(a.g, tile + gridDim.x, a.P, a.g.spt);
-    run_zadj(a, buf, tile, xf);
+    xf(buf, S);
+    pw_adj_combine(a, buf, tile);
+    __syncthreads();
+    pipe.issue(a.g, tile + gridDim.x, a.P);
+    xf(buf, S);
+    tile_store<T, XF::W, FAST>(a.g, tile, buf, a.P);
     __syncthreads();
   }
 }
 
 // One transform along one axis, src -> dst (may alias), optional Neumann
 // point weights before (divide) or after (multiply).
-template <typename T, class XF>
-__global__ __launch_bounds__(XF::THREADS, 4) void k_single_m(SingleArgs<T> a, MfmaAxisDev ax) {
+template <typename T, class XF, bool FAST>
+__global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(SingleArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const Geom& g = a.g;
   const int ne = g.n * g.W;
-  TilePrefetch<T, MfPrefetch<T>::fwd> pf;
-  pf.issue(g, blockIdx.x, a.src, g.spt);
+  TilePipe<T, XF::W, FAST> pipe;
+  pipe.issue(g, blockIdx.x, a.src);
   for (long long tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
-    pf.commit(g, tile, a.src, buf, g.spt);
+    pipe.commit(g, tile, a.src, buf);
     __syncthreads();
-    pf.issue(g, tile + gridDim.x, a.src, g.spt);
+    pipe.issue(g, tile + gridDim.x, a.src);
     const TileRef tr = tile_ref(g, tile);
     if (a.pre_divide_w) {
       for (int e = threadIdx.x; e < ne; e += blockDim.x) {
@@ -557,7 +919,7 @@ __global__ __launch_bounds__(XF::THREADS, 4) void k_single_m(SingleArgs<T> a, Mf
       }
       __syncthreads();
     }
-    store_tile_fast(g, tile, buf, a.dst, g.spt);
+    tile_store<T, XF::W, FAST>(g, tile, buf, a.dst);
     __syncthreads();
   }
 }

@@ -16,8 +16,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <cstdint>
+#include <initializer_list>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/sfrde.h"
@@ -222,6 +225,7 @@ void make_geom(sfrde_plan_s* p, int axis) {
   for (int a = 0; a < axis; ++a) inner *= p->n[a];
   g.n = (int)n;
   g.spt = p->S;
+  g.fast = 0;
   g.inner = inner;
   g.total = p->total;
   // Tile width: a power of two with n*W <= KMAX*NTHREADS, the tile of all
@@ -373,6 +377,14 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
     g.tpo = (g.inner + W - 1) / W;
     g.ntiles = g.outer * g.tpo;
   }
+  // vector tile paths of the FP32 engine (their thread layouts assume these)
+  if (f32 && g.inner == 1)
+    g.fast = (g.n == 64 || g.n == 128 || g.n == 256) && (long long)p->S * g.n <= 512 &&
+             (long long)p->S * g.n >= 128 && g.outer % W == 0;
+  else if (f32)
+    g.fast = g.inner % W == 0 && g.n % 64 == 0 && g.n <= 256;
+  else
+    g.fast = 0;
   MfmaAxisDev& ax = p->mfax[axis];
   ax.hK = t.hK;
   ax.RBe = t.RBe;
@@ -393,8 +405,7 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: keep the dense kernels
   p->lds_m[axis] = lds;
   // persistent grid: as many blocks as fit on the CUs at once
-  const long long per_cu = std::max<long long>(
-      1, std::min<long long>((long long)(160 * 1024 / lds), MF_THREADS / threads));
+  const long long per_cu = 1;
   p->grid_m[axis] = (unsigned)std::min<long long>(g.ntiles, (long long)p->n_cu * per_cu);
   // fragment-ordered split matrices
   if (p->dtype == SFRDE_F32) {
@@ -433,12 +444,26 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
 
 template <typename T>
 int set_lds_attrs(size_t bytes) {
-  const void* fns[] = {reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>>),
-                       reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>>),
-                       reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>>),
-                       reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>>),
-                       reinterpret_cast<const void*>(&k_single_m<T, XfX<T>>),
-                       reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>>)};
+  std::vector<const void*> fns = {
+      reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>, false>),
+      reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, -1, false>),
+      reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, false>),
+      reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, false>),
+      reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, false>),
+      reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, false>)};
+  if constexpr (std::is_same<T, float>::value) {
+    const void* fast[] = {reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>, true>),
+                          reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, -1, true>),
+                          reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 0, true>),
+                          reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 1, true>),
+                          reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 2, true>),
+                          reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 3, true>),
+                          reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, true>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true>),
+                          reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true>),
+                          reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true>)};
+    for (const void* f : fast) fns.push_back(f);
+  }
   for (const void* f : fns)
     HIPCHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   return SFRDE_OK;
@@ -473,6 +498,16 @@ StageArgs<T> stage_args(sfrde_plan_s* p, int axis, void* P) {
   return a;
 }
 
+// The FP32 engine's vector tile paths: the axis geometry allows them and
+// every field pointer the kernel moves tiles of is 16-byte aligned.
+template <typename T>
+bool use_fast(const sfrde_plan_s* p, int axis, std::initializer_list<const void*> ptrs) {
+  if (!std::is_same<T, float>::value || !p->geom_m[axis].fast) return false;
+  for (const void* q : ptrs)
+    if (reinterpret_cast<uintptr_t>(q) & 15u) return false;
+  return true;
+}
+
 template <typename T>
 int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre_div, int post_mul) {
   SingleArgs<T> a{};
@@ -487,16 +522,35 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
   a.n1 = p->n[1];
   a.n2 = p->n[2];
   const long long pk = prof_start(p, KC_Y);
-  if (p->use_m[axis])
-    if (axis == 0)
-      hipLaunchKernelGGL((k_single_m<T, XfX<T>>), dim3(p->grid_m[axis]), dim3(XfX<T>::THREADS),
-                         p->lds_m[axis], p->stream, a, p->mfax[axis]);
-    else
-      hipLaunchKernelGGL((k_single_m<T, XfZ<T>>), dim3(p->grid_m[axis]), dim3(XfZ<T>::THREADS),
-                         p->lds_m[axis], p->stream, a, p->mfax[axis]);
-  else
+  if (p->use_m[axis]) {
+    const dim3 grid(p->grid_m[axis]);
+    const size_t lds = p->lds_m[axis];
+    const bool fast = use_fast<T>(p, axis, {src, dst});
+    if (axis == 0) {
+      const dim3 block(XfX<T>::THREADS);
+      if constexpr (std::is_same<T, float>::value)
+        if (fast) {
+          hipLaunchKernelGGL((k_single_m<T, XfX<T>, true>), grid, block, lds, p->stream, a,
+                             p->mfax[axis]);
+          goto launched;
+        }
+      hipLaunchKernelGGL((k_single_m<T, XfX<T>, false>), grid, block, lds, p->stream, a,
+                         p->mfax[axis]);
+    } else {
+      const dim3 block(XfZ<T>::THREADS);
+      if constexpr (std::is_same<T, float>::value)
+        if (fast) {
+          hipLaunchKernelGGL((k_single_m<T, XfZ<T>, true>), grid, block, lds, p->stream, a,
+                             p->mfax[axis]);
+          goto launched;
+        }
+      hipLaunchKernelGGL((k_single_m<T, XfZ<T>, false>), grid, block, lds, p->stream, a,
+                         p->mfax[axis]);
+    }
+  } else
     hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[axis],
                        p->stream, a);
+launched:
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
@@ -529,15 +583,39 @@ int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
   a.t = t;
   a.st_phys = st_phys;
   const long long pk = prof_start(p, KC_X);
-  if (p->use_m[0])
-    hipLaunchKernelGGL((k_xstage_m<T, XfX<T>>), dim3(p->grid_m[0]), dim3(XfX<T>::THREADS),
-                       p->lds_m[0], p->stream, a, p->mfax[0]);
-  else
+  if (p->use_m[0]) {
+    const dim3 grid(p->grid_m[0]), block(XfX<T>::THREADS);
+    if (use_fast<T>(p, 0, {p->P, st_phys}))
+      hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, std::is_same<T, float>::value>), grid, block,
+                         p->lds_m[0], p->stream, a, p->mfax[0]);
+    else
+      hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
+                         p->mfax[0]);
+  } else
     hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
                        p->stream, a);
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
+}
+
+// The four forward stages of FP32 plans have their own Z kernels.
+template <typename T>
+void launch_zstage_m(bool fast, int mode, dim3 grid, size_t lds, hipStream_t st,
+                     const StageArgs<T>& a, const MfmaAxisDev& ax) {
+  const dim3 block(XfZ<T>::THREADS);
+  if constexpr (std::is_same<T, float>::value) {
+    if (fast) {
+      switch (mode) {
+        case 0: hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, 0, true>), grid, block, lds, st, a, ax); return;
+        case 1: hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, 1, true>), grid, block, lds, st, a, ax); return;
+        case 2: hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, 2, true>), grid, block, lds, st, a, ax); return;
+        case 3: hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, 3, true>), grid, block, lds, st, a, ax); return;
+        default: hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, -1, true>), grid, block, lds, st, a, ax); return;
+      }
+    }
+  }
+  hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, -1, false>), grid, block, lds, st, a, ax);
 }
 
 template <typename T>
@@ -550,8 +628,8 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat)
   a.st_fhat = st_fhat;
   const long long pk = prof_start(p, KC_Z);
   if (p->use_m[ax])
-    hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>>), dim3(p->grid_m[ax]), dim3(XfZ<T>::THREADS),
-                       p->lds_m[ax], p->stream, a, p->mfax[ax]);
+    launch_zstage_m<T>(use_fast<T>(p, ax, {p->P, src}), mode, dim3(p->grid_m[ax]), p->lds_m[ax],
+                       p->stream, a, p->mfax[ax]);
   else
     hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
                        p->stream, a);
@@ -677,10 +755,15 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
   a.st_phys = st.phys;
   a.rp_acc = p->rp_acc;
   const long long pk = prof_start(p, KC_XADJ);
-  if (p->use_m[0])
-    hipLaunchKernelGGL((k_xadj_m<T, XfX<T>>), dim3(p->grid_m[0]), dim3(XfX<T>::THREADS),
-                       p->lds_m[0], p->stream, a, p->mfax[0]);
-  else
+  if (p->use_m[0]) {
+    const dim3 grid(p->grid_m[0]), block(XfX<T>::THREADS);
+    if (use_fast<T>(p, 0, {p->Pa}))
+      hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, std::is_same<T, float>::value>), grid, block,
+                         p->lds_m[0], p->stream, a, p->mfax[0]);
+    else
+      hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
+                         p->mfax[0]);
+  } else
     hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
                        p->stream, a);
   prof_stop(p, pk);
@@ -701,10 +784,15 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
   }
   if (!p->G) a.dcoef = nullptr;
   const long long pk = prof_start(p, KC_ZADJ);
-  if (p->use_m[ax])
-    hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>>), dim3(p->grid_m[ax]), dim3(XfZ<T>::THREADS),
-                       p->lds_m[ax], p->stream, a, p->mfax[ax]);
-  else
+  if (p->use_m[ax]) {
+    const dim3 grid(p->grid_m[ax]), block(XfZ<T>::THREADS);
+    if (use_fast<T>(p, ax, {p->Pa}))
+      hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, std::is_same<T, float>::value>), grid, block,
+                         p->lds_m[ax], p->stream, a, p->mfax[ax]);
+    else
+      hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, false>), grid, block, p->lds_m[ax], p->stream, a,
+                         p->mfax[ax]);
+  } else
     hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
                        p->stream, a);
   prof_stop(p, pk);
