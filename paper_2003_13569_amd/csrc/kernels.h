@@ -423,12 +423,11 @@ struct StageArgs {
 // Forward reaction: buf holds the stage value (physical); replaced by f.
 // Walks the LDS tile row by row (lanes w fastest); the global index is only
 // formed when stage values are stored.
-template <typename T>
-__device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long long tile) {
+template <typename T, int NS>
+__device__ __forceinline__ bool pw_reaction_n(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
   const TileRef tr = tile_ref(g, tile);
   const RxnT<T> rx(a.rxn);
-  const int S = a.S;
   const int sstride = g.n * g.pitch;
   bool bad = false;
   const int ne = g.n << g.wshift;
@@ -436,19 +435,36 @@ __device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long 
     const int j = e >> g.wshift, w = e & (g.W - 1);
     if (w >= tr.wvalid) continue;
     T* cell = buf + j * g.pitch + w;
-    T u[MAX_SPECIES], f[MAX_SPECIES];
-    for (int s = 0; s < S; ++s) u[s] = cell[s * sstride];
+    T u[NS], f[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) u[s] = cell[s * sstride];
     if (a.st_phys) {
       const long long idx = tr.base + (long long)j * tr.rs + (long long)w * tr.cs;
-      for (int s = 0; s < S; ++s) a.st_phys[((long long)a.mode * S + s) * g.total + idx] = u[s];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) a.st_phys[((long long)a.mode * NS + s) * g.total + idx] = u[s];
     }
-    rxn_eval_t(rx, u, f);
-    for (int s = 0; s < S; ++s) {
+    rxn_eval_t<T, NS>(rx, u, f);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
       bad |= !isfinite(u[s]) || !isfinite(f[s]);
       cell[s * sstride] = f[s];
     }
   }
   return bad;
+}
+
+template <typename T>
+__device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long long tile) {
+  switch (a.S) {
+    case 1:
+      return pw_reaction_n<T, 1>(a, buf, tile);
+    case 2:
+      return pw_reaction_n<T, 2>(a, buf, tile);
+    case 3:
+      return pw_reaction_n<T, 3>(a, buf, tile);
+    default:
+      return pw_reaction_n<T, 4>(a, buf, tile);
+  }
 }
 
 // Coefficients a forward stage needs, as c0..c3:
@@ -693,12 +709,11 @@ __device__ __forceinline__ void pw_combine_fast(const StageArgs<T>& a, T* buf, l
 // Adjoint reaction: buf holds the cotangent of f(stage value) (physical);
 // replaced by J^T of it at the stored stage value. Reaction-parameter
 // partials are added to pacc (weighted by the Neumann point weights).
-template <typename T>
-__device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, long long tile,
-                                                double* pacc) {
+template <typename T, int NS>
+__device__ __forceinline__ void pw_adj_reaction_n(const StageArgs<T>& a, T* buf, long long tile,
+                                                  double* pacc) {
   const Geom& g = a.g;
   const TileRef tr = tile_ref(g, tile);
-  const int S = a.S;
   const bool want_p = a.rp_acc != nullptr;
   const int ne = g.n * g.W;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
@@ -706,14 +721,35 @@ __device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, l
     unpack(g, e, j, w);
     long long idx;
     if (!elem(g, tr, j, w, idx)) continue;
-    T u[MAX_SPECIES], gg[MAX_SPECIES], o[MAX_SPECIES];
-    for (int s = 0; s < S; ++s) {
+    T u[NS], gg[NS], o[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
       gg[s] = buf[(s * g.n + j) * g.pitch + w];
-      u[s] = a.st_phys[((long long)a.mode * S + s) * g.total + idx];
+      u[s] = a.st_phys[((long long)a.mode * NS + s) * g.total + idx];
     }
     const double wgt = a.neumann ? point_weight(idx, a.n0, a.n1, a.n2) : 1.0;
-    rxn_adjoint(a.rxn, u, gg, o, wgt, pacc, want_p);
-    for (int s = 0; s < S; ++s) buf[(s * g.n + j) * g.pitch + w] = o[s];
+    rxn_adjoint<T, NS>(a.rxn, u, gg, o, wgt, pacc, want_p);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) buf[(s * g.n + j) * g.pitch + w] = o[s];
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, long long tile,
+                                                double* pacc) {
+  switch (a.S) {
+    case 1:
+      pw_adj_reaction_n<T, 1>(a, buf, tile, pacc);
+      break;
+    case 2:
+      pw_adj_reaction_n<T, 2>(a, buf, tile, pacc);
+      break;
+    case 3:
+      pw_adj_reaction_n<T, 3>(a, buf, tile, pacc);
+      break;
+    default:
+      pw_adj_reaction_n<T, 4>(a, buf, tile, pacc);
+      break;
   }
 }
 
@@ -955,8 +991,8 @@ template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   DenseXf<T> xf{&a.g, a.Mt};
-  double pacc[MAX_PARAMS];
-  for (int k = 0; k < MAX_PARAMS; ++k) pacc[k] = 0.0;
+  double pacc[RXN_NP_MAX];
+  for (int k = 0; k < RXN_NP_MAX; ++k) pacc[k] = 0.0;
   body_xadj<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf, pacc);
   if (a.rp_acc) {
     __syncthreads();

@@ -840,8 +840,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
-  double pacc[MAX_PARAMS];
-  for (int k = 0; k < MAX_PARAMS; ++k) pacc[k] = 0.0;
+  double pacc[RXN_NP_MAX];
+  for (int k = 0; k < RXN_NP_MAX; ++k) pacc[k] = 0.0;
   const int S = a.g.spt;
   TilePipe<T, XF::W, FAST> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);

@@ -9,6 +9,7 @@ namespace sfrde {
 enum { RXN_LINEAR = 0, RXN_FHN = 1, RXN_GRAY_SCOTT = 2, RXN_SCHNAKENBERG = 3, RXN_GM = 4 };
 constexpr int MAX_SPECIES = 4;
 constexpr int MAX_PARAMS = 16;
+constexpr int RXN_NP_MAX = 5;  // parameters of any of the models (linear: one per species)
 
 struct Rxn {
   int kind;
@@ -29,38 +30,42 @@ struct RxnT {
   }
 };
 
-template <typename T>
+// NS = number of species, fixed at compile time so that the per-point
+// arrays stay in registers.
+template <typename T, int NS>
 __device__ __forceinline__ void rxn_eval_t(const RxnT<T>& r, const T* u, T* f) {
   switch (r.kind) {
     case RXN_LINEAR:
-      for (int s = 0; s < r.S; ++s) f[s] = r.lin[s] * u[s];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) f[s] = r.lin[s] * u[s];
       break;
-    case RXN_FHN: {
-      const T x = u[0], v = u[1];
-      f[0] = x * (T(1) - x) * (x - r.p[0]) - v;
-      f[1] = r.p[1] * (r.p[2] * x - r.p[3] * v - r.p[4]);
+    default:
+      if constexpr (NS == 2) {
+        const T x = u[0], v = u[1];
+        switch (r.kind) {
+          case RXN_FHN:
+            f[0] = x * (T(1) - x) * (x - r.p[0]) - v;
+            f[1] = r.p[1] * (r.p[2] * x - r.p[3] * v - r.p[4]);
+            break;
+          case RXN_GRAY_SCOTT: {
+            const T xvv = x * v * v;
+            f[0] = -xvv + r.p[0] * (T(1) - x);
+            f[1] = xvv - (r.p[0] + r.p[1]) * v;
+            break;
+          }
+          case RXN_SCHNAKENBERG: {
+            const T xxv = x * x * v;
+            f[0] = r.p[0] * (r.p[1] - x + xxv);
+            f[1] = r.p[0] * (r.p[2] - xxv);
+            break;
+          }
+          default:  // Gierer-Meinhardt
+            f[0] = r.p[0] - r.p[1] * x + r.p[2] * x * x / v;
+            f[1] = r.p[3] * x * x - r.p[4] * v;
+            break;
+        }
+      }
       break;
-    }
-    case RXN_GRAY_SCOTT: {
-      const T x = u[0], v = u[1];
-      const T xvv = x * v * v;
-      f[0] = -xvv + r.p[0] * (T(1) - x);
-      f[1] = xvv - (r.p[0] + r.p[1]) * v;
-      break;
-    }
-    case RXN_SCHNAKENBERG: {
-      const T x = u[0], v = u[1];
-      const T xxv = x * x * v;
-      f[0] = r.p[0] * (r.p[1] - x + xxv);
-      f[1] = r.p[0] * (r.p[2] - xxv);
-      break;
-    }
-    default: {
-      const T x = u[0], v = u[1];
-      f[0] = r.p[0] - r.p[1] * x + r.p[2] * x * x / v;
-      f[1] = r.p[3] * x * x - r.p[4] * v;
-      break;
-    }
   }
 }
 
@@ -106,16 +111,19 @@ __device__ __forceinline__ void rxn_eval(const Rxn& r, const T* u, T* f) {
 
 // out = J_f(u)^T g (out_r = sum_s g_s d f_s / d u_r), and
 // pacc[k] += wgt * sum_s g_s d f_s / d p_k.
-template <typename T>
+template <typename T, int NS>
 __device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g, T* out,
                                             double wgt, double* pacc, bool want_p) {
+  if (r.kind == RXN_LINEAR) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      out[s] = T(r.p[s]) * g[s];
+      if (want_p) pacc[s] += wgt * double(g[s] * u[s]);
+    }
+    return;
+  }
+  if constexpr (NS == 2) {
   switch (r.kind) {
-    case RXN_LINEAR:
-      for (int s = 0; s < r.S; ++s) {
-        out[s] = T(r.p[s]) * g[s];
-        if (want_p) pacc[s] += wgt * double(g[s] * u[s]);
-      }
-      break;
     case RXN_FHN: {
       const T mu = T(r.p[0]), eps = T(r.p[1]), beta = T(r.p[2]), gam = T(r.p[3]), dlt = T(r.p[4]);
       const T x = u[0], v = u[1], gu = g[0], gv = g[1];
@@ -172,6 +180,7 @@ __device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g
       }
       break;
     }
+  }
   }
 }
 
