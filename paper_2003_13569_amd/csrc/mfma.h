@@ -155,12 +155,12 @@ __device__ __forceinline__ float row16_max(float m) {
 }
 
 // Eight waves; wave w owns row blocks 2w and 2w + 1 (of E, then of O), so
-// two 512-thread blocks share a CU and one block's memory waits overlap the
-// other's arithmetic. W = 32 lines for strided axes (128-byte rows), 16 for
-// the contiguous x axis (whose tiles hold every species).
-template <int W_>
+// one 512-thread block per CU has 256 registers per lane for the fragments
+// and the prefetched tile. W = 32 lines (128-byte rows on strided axes).
+template <int W_, bool XAX_>
 struct MfmaXfF32 {
   static constexpr int W = W_;
+  static constexpr bool XAX = XAX_;  // x-axis tiles (every species) rather than strided ones
   static constexpr int THREADS = 512;
   static constexpr int MIN_WAVES_PER_EU = 2;  // one block per CU, 256 registers per lane
   static constexpr int P = W + 1;             // LDS row pitch of the tile
@@ -365,6 +365,7 @@ struct MfmaXfF64 {
   static constexpr int W = 16;
   static constexpr int THREADS = MF_THREADS;
   static constexpr int MIN_WAVES_PER_EU = 4;
+  static constexpr bool XAX = false;  // generic tile paths on every axis
   const Geom* g;
   const MfmaAxisDev* ax;
   double* fb;
@@ -431,8 +432,8 @@ template <typename T>
 struct XfSel;
 template <>
 struct XfSel<float> {
-  using X = MfmaXfF32<16>;
-  using Z = MfmaXfF32<32>;
+  using X = MfmaXfF32<32, true>;
+  using Z = MfmaXfF32<32, false>;
 };
 template <>
 struct XfSel<double> {
@@ -503,11 +504,13 @@ struct TileIO<float, 32> {
   }
 };
 
-template <>
-struct TileIO<float, 16> {
-  static constexpr int P = 17, MAXV = 4;  // vectors per thread: S * 16 * n / 4 / 512 <= 4
-  // vector v of species s -> offset within the species' field from the tile
-  // base, and LDS offset
+// x-axis tiles (inner == 1): W lines of every species. Vector v of species
+// s: 16 consecutive vectors of each of 4 lines per 64 vectors, so that the
+// four scalar LDS writes of a vector land in distinct banks across a wave.
+template <int W>
+struct XTileIO {
+  static constexpr int P = W + 1;
+  static constexpr int MAXV = W / 4;  // vectors per thread: S * W * n / 4 / 512 <= W / 4
   __device__ __forceinline__ static int log2n64(const Geom& g) {
     return g.n == 256 ? 2 : (g.n == 128 ? 1 : 0);
   }
@@ -519,9 +522,13 @@ struct TileIO<float, 16> {
     go = line * g.n + j;
     lo = (s * g.n + j) * P + line;
   }
+  // log2 of the vectors per species, W n / 4
+  __device__ __forceinline__ static int vshift(const Geom& g) {
+    return log2n64(g) + (W == 32 ? 9 : 8);
+  }
   __device__ __forceinline__ static void issue(const Geom& g, const TileRef& tr, const float* src,
                                                float4* v) {
-    const int sh = log2n64(g) + 8;  // log2 of the vectors per species, 4n
+    const int sh = vshift(g);
     const int nv = g.spt << sh;  // vectors in the tile, a multiple of 512
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) {
@@ -533,7 +540,7 @@ struct TileIO<float, 16> {
     }
   }
   __device__ __forceinline__ static void commit(const Geom& g, const float4* v, float* buf) {
-    const int sh = log2n64(g) + 8;
+    const int sh = vshift(g);
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) {
       const int q = threadIdx.x + 512 * k, s = q >> sh;
@@ -550,7 +557,7 @@ struct TileIO<float, 16> {
   }
   __device__ __forceinline__ static void store(const Geom& g, const TileRef& tr, const float* buf,
                                                float* dst) {
-    const int sh = log2n64(g) + 8;
+    const int sh = vshift(g);
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) {
       const int q = threadIdx.x + 512 * k, s = q >> sh;
@@ -570,24 +577,28 @@ struct TileIO<float, 16> {
 // 16-byte aligned) move tiles with TileIO only; the others with the generic
 // paths, loading in place. Keeping the two apart keeps the compiler's wait
 // counts exact on the fast path.
-template <typename T, int W, bool FAST>
+template <typename T, int W, bool FAST, bool XAX>
 struct TilePipe {
-  float4 v[4];
+  using IO = typename std::conditional<XAX && std::is_same<T, float>::value, XTileIO<W>,
+                                       TileIO<T, W>>::type;
+  float4 v[XAX ? W / 4 : 4];
   __device__ __forceinline__ void issue(const Geom& g, long long tile, const T* src) {
-    if (FAST && tile < g.ntiles) TileIO<T, W>::issue(g, tile_ref(g, tile), src, v);
+    if (FAST && tile < g.ntiles) IO::issue(g, tile_ref(g, tile), src, v);
   }
   __device__ __forceinline__ void commit(const Geom& g, long long tile, const T* src, T* buf) {
     if (FAST)
-      TileIO<T, W>::commit(g, v, buf);
+      IO::commit(g, v, buf);
     else
       load_tile_fast(g, tile, src, buf, g.spt);
   }
 };
 
-template <typename T, int W, bool FAST>
+template <typename T, int W, bool FAST, bool XAX>
 __device__ __forceinline__ void tile_store(const Geom& g, long long tile, const T* buf, T* dst) {
+  using IO = typename std::conditional<XAX && std::is_same<T, float>::value, XTileIO<W>,
+                                       TileIO<T, W>>::type;
   if (FAST)
-    TileIO<T, W>::store(g, tile_ref(g, tile), buf, dst);
+    IO::store(g, tile_ref(g, tile), buf, dst);
   else
     store_tile_fast(g, tile, buf, dst, g.spt);
 }
@@ -783,7 +794,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const int S = a.g.spt;
-  TilePipe<T, XF::W, FAST> pipe;
+  TilePipe<T, XF::W, FAST, true> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
     pipe.commit(a.g, tile, a.P, buf);
@@ -793,7 +804,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
     if (pw_reaction(a, buf, tile)) a.flag[0] = 1;
     __syncthreads();
     xf(buf, S);
-    tile_store<T, XF::W, FAST>(a.g, tile, buf, a.P);
+    tile_store<T, XF::W, FAST, true>(a.g, tile, buf, a.P);
     __syncthreads();
   }
 }
@@ -808,7 +819,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
   const T* src = a.src ? a.src : a.P;
   const int S = a.g.spt;
   constexpr bool PRE = FAST && MODE >= 0 && std::is_same<T, float>::value && XF::W == 32;
-  TilePipe<T, XF::W, FAST> pipe;
+  TilePipe<T, XF::W, FAST, false> pipe;
   pipe.issue(a.g, blockIdx.x, src);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
     pipe.commit(a.g, tile, src, buf);
@@ -830,7 +841,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
     __syncthreads();
     pipe.issue(a.g, tile + gridDim.x, src);
     xf(buf, S);
-    tile_store<T, XF::W, FAST>(a.g, tile, buf, a.P);
+    tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
     __syncthreads();
   }
 }
@@ -843,7 +854,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
   double pacc[RXN_NP_MAX];
   for (int k = 0; k < RXN_NP_MAX; ++k) pacc[k] = 0.0;
   const int S = a.g.spt;
-  TilePipe<T, XF::W, FAST> pipe;
+  TilePipe<T, XF::W, FAST, true> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
     pipe.commit(a.g, tile, a.P, buf);
@@ -853,7 +864,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
     __syncthreads();
     pipe.issue(a.g, tile + gridDim.x, a.P);
     xf(buf, S);
-    tile_store<T, XF::W, FAST>(a.g, tile, buf, a.P);
+    tile_store<T, XF::W, FAST, true>(a.g, tile, buf, a.P);
     __syncthreads();
   }
   if (a.rp_acc) block_add_partials(reinterpret_cast<double*>(smem_raw), pacc, a.rxn.np, a.rp_acc);
@@ -865,7 +876,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const int S = a.g.spt;
-  TilePipe<T, XF::W, FAST> pipe;
+  TilePipe<T, XF::W, FAST, false> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
     pipe.commit(a.g, tile, a.P, buf);
@@ -875,7 +886,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
     __syncthreads();
     pipe.issue(a.g, tile + gridDim.x, a.P);
     xf(buf, S);
-    tile_store<T, XF::W, FAST>(a.g, tile, buf, a.P);
+    tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
     __syncthreads();
   }
 }
@@ -889,7 +900,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const Geom& g = a.g;
   const int ne = g.n * g.W;
-  TilePipe<T, XF::W, FAST> pipe;
+  TilePipe<T, XF::W, FAST, XF::XAX> pipe;
   pipe.issue(g, blockIdx.x, a.src);
   for (long long tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
     pipe.commit(g, tile, a.src, buf);
@@ -919,7 +930,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
       }
       __syncthreads();
     }
-    tile_store<T, XF::W, FAST>(g, tile, buf, a.dst);
+    tile_store<T, XF::W, FAST, XF::XAX>(g, tile, buf, a.dst);
     __syncthreads();
   }
 }

@@ -380,7 +380,7 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   // vector tile paths of the FP32 engine (their thread layouts assume these)
   if (f32 && g.inner == 1)
     g.fast = (g.n == 64 || g.n == 128 || g.n == 256) && (long long)p->S * g.n <= 512 &&
-             (long long)p->S * g.n >= 128 && g.outer % W == 0;
+             (long long)p->S * g.n >= 64 && g.outer % W == 0;
   else if (f32)
     g.fast = g.inner % W == 0 && g.n % 64 == 0 && g.n <= 256;
   else
