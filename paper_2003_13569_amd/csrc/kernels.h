@@ -409,6 +409,13 @@ struct StageArgs {
   double t;
   T cs;             // product of the per-axis inverse scales
   T tau;            // time step
+  // L formed in the kernel from the per-axis eigenvalues (FP32 vector Z
+  // kernels): L = kt_s Lambda^ha_s, Lambda the sum of the axis eigenvalues.
+  const double* lam[3];
+  T kt[MAX_SPECIES];  // kappa_s tau
+  T ha[MAX_SPECIES];  // alpha_s / 2
+  int lfly;
+  int lam_off;        // byte offset of the eigenvalue tables in dynamic LDS
   int S;
   int mode;         // stage 0..3, or MODE_INIT / MODE_RESTORE
   int last;         // adjoint: this is step 0 (output u-bar, not phi3 u-bar)

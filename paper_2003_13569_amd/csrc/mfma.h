@@ -610,18 +610,50 @@ __device__ __forceinline__ void tile_store(const Geom& g, long long tile, const 
 template <int MODE>
 struct StageLoads {
   float4 L[4], r1[4], r2[4];
-  __device__ __forceinline__ void issue(const StageArgs<float>& a, const TileRef& tr) {
+  __device__ __forceinline__ void issue(const StageArgs<float>& a, const TileRef& tr,
+                                        long long tile, const float* lam_lds) {
     using IO = TileIO<float, 32>;
-    const long long inner = a.g.inner;
+    const Geom& g = a.g;
+    const long long inner = g.inner;
     const long long i0 = tr.base + IO::row0() * inner + IO::lane4();
     const float* p1 = MODE <= 1 ? a.uhat : a.acc;
     const float* p2 = MODE == 1 ? a.acc : a.ctil;
 #pragma unroll
     for (int k = 0; k < IO::MAXK; ++k) {
-      const long long i = i0 + (64 * k < a.g.n ? k : 0) * IO::RSTEP * inner;
-      L[k] = *reinterpret_cast<const float4*>(a.ltab + i);
+      const long long i = i0 + (64 * k < g.n ? k : 0) * IO::RSTEP * inner;
+      if (!a.lfly) L[k] = *reinterpret_cast<const float4*>(a.ltab + i);
       r1[k] = *reinterpret_cast<const float4*>(p1 + i);
       if (MODE == 1 || MODE == 2) r2[k] = *reinterpret_cast<const float4*>(p2 + i);
+    }
+    if (a.lfly) {
+      // L = kt_s Lambda^ha_s from the eigenvalue tables in LDS: [n0] x, [n1] y,
+      // then the transformed (last) axis. The last axis has one outer block
+      // per species.
+      const long long o = tile / g.tpo;
+      const int s = (int)o;
+      const int ib = (int)(tile - o * g.tpo) * 32 + IO::lane4();
+      const int n0 = (int)a.n0, n1 = (int)a.n1;
+      const bool three = a.n2 > 1;
+      const float* lz = lam_lds + n0 + (three ? n1 : 0);
+      // the four lanes of a vector share y (n0 is a multiple of 4)
+      const int y = three ? ib / n0 : 0;
+      const float* lx = lam_lds + (three ? ib - y * n0 : ib);
+      const float ly = three ? lam_lds[n0 + y] : 0.f;
+      float lxy[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) lxy[e] = lx[e] + ly;
+      const float kt = a.kt[s], ha = a.ha[s];
+#pragma unroll
+      for (int k = 0; k < IO::MAXK; ++k) {
+        const float lr = lz[IO::row0() + 64 * (64 * k < g.n ? k : 0)];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          // Lambda >= the smallest nonzero eigenvalue, far from denormals:
+          // the hardware log2 / exp2 (about 1 ulp) suffice
+          const float lam = lxy[e] + lr;
+          vset<float>(L[k], e, lam > 0.f ? kt * __builtin_amdgcn_exp2f(ha * __builtin_amdgcn_logf(lam)) : 0.f);
+        }
+      }
     }
   }
 };
@@ -819,6 +851,14 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
   const T* src = a.src ? a.src : a.P;
   const int S = a.g.spt;
   constexpr bool PRE = FAST && MODE >= 0 && std::is_same<T, float>::value && XF::W == 32;
+  // eigenvalue tables for L formed in the kernel
+  float* lam_lds = reinterpret_cast<float*>(smem_raw + a.lam_off);
+  if (PRE && a.lfly) {
+    const int nx = (int)a.n0, ny = (int)a.n1, nz = a.n2 > 1 ? (int)a.n2 : 0;
+    for (int i = threadIdx.x; i < nx + ny + nz; i += blockDim.x)
+      lam_lds[i] = float(i < nx ? a.lam[0][i] : (i < nx + ny ? a.lam[1][i - nx] : a.lam[2][i - nx - ny]));
+    __syncthreads();
+  }
   TilePipe<T, XF::W, FAST, false> pipe;
   pipe.issue(a.g, blockIdx.x, src);
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
@@ -826,9 +866,9 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
     __syncthreads();
     if constexpr (PRE) {
       const TileRef tr = tile_ref(a.g, tile);
-      const bool pre = a.ltab && S == 1 && !a.src;
+      const bool pre = (a.ltab || a.lfly) && S == 1 && !a.src;
       StageLoads<(PRE ? MODE : 0)> ld;
-      if (pre) ld.issue(a, tr);
+      if (pre) ld.issue(a, tr, tile, lam_lds);
       xf(buf, S);
       if (pre)
         combine_pre(a, buf, tr, ld);

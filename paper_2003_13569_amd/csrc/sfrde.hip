@@ -95,6 +95,8 @@ struct sfrde_plan_s {
   void* coef = nullptr;
   void* dcoef = nullptr;
   void* ltab = nullptr;  // P13 plans: L per species and point
+  bool lfly = false;     // FP32 P13 Z kernels form L from the eigenvalues
+  size_t lam_off = 0;    // LDS byte offset of the eigenvalue tables (last axis kernels)
   void* P = nullptr;
   void* uhat = nullptr;
   void* ctil = nullptr;
@@ -480,6 +482,13 @@ StageArgs<T> stage_args(sfrde_plan_s* p, int axis, void* P) {
   a.ltab = (const T*)p->ltab;
   a.dcoef = (const T*)p->dcoef;
   a.tau = T(p->dt);
+  for (int k = 0; k < 3; ++k) a.lam[k] = p->lam[k];
+  for (int s = 0; s < p->S; ++s) {
+    a.kt[s] = T(p->kappa[s] * p->dt);
+    a.ha[s] = T(0.5 * p->alpha[s]);
+  }
+  a.lfly = p->lfly && axis == p->ndim - 1;
+  a.lam_off = (int)p->lam_off;
   a.uhat = (T*)p->uhat;
   a.ctil = (T*)p->ctil;
   a.acc = (T*)p->acc;
@@ -1045,10 +1054,25 @@ int build_plan(sfrde_plan_s* p) {
     HIPCHECK(hipMemcpy(p->lam[a], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   size_t lds_max = 0;
-  for (int a = 0; a < p->ndim; ++a) {
-    TRY(setup_mfma_axis(p, a));
-    lds_max = std::max(lds_max, p->lds_m[a]);
+  for (int a = 0; a < p->ndim; ++a) TRY(setup_mfma_axis(p, a));
+  {
+    // FP32 P13 plans whose last axis runs the vector Z kernels form L there
+    // from the eigenvalue tables (kept in LDS as floats) instead of reading
+    // an L table (SFRDE_COEF=table keeps the table).
+    const int za = p->ndim - 1;
+    const char* cenv = getenv("SFRDE_COEF");
+    const bool table = cenv && strcmp(cenv, "table") == 0;
+    long long nsum = 0;
+    for (int a = 0; a < p->ndim; ++a) nsum += p->n[a];
+    const size_t extra = (size_t)nsum * sizeof(float);
+    if (p->dtype == SFRDE_F32 && p->scheme == SFRDE_SCHEME_P13 && !table && p->use_m[za] &&
+        p->geom_m[za].fast && p->n[0] % 4 == 0 && p->lds_m[za] + extra <= 160 * 1024) {
+      p->lfly = true;
+      p->lam_off = (p->lds_m[za] + 15) / 16 * 16;
+      p->lds_m[za] = p->lam_off + extra;
+    }
   }
+  for (int a = 0; a < p->ndim; ++a) lds_max = std::max(lds_max, p->lds_m[a]);
   if (lds_max > 0) {
     if (p->dtype == SFRDE_F32)
       TRY(set_lds_attrs<float>(lds_max));
