@@ -495,12 +495,13 @@ struct TileIO<float, 32> {
     const int r0 = row0(), w4 = lane4();
     const long long inner = g.inner;
     float* dp = dst + tr.base + r0 * inner + w4;
+    // straight-line stores: rows past n store row block 0 again (same values)
 #pragma unroll
-    for (int k = 0; k < MAXK; ++k)
-      if (64 * k < g.n) {
-        const float* b = buf + (r0 + RSTEP * k) * P + w4;
-        *reinterpret_cast<float4*>(dp + k * RSTEP * inner) = make_float4(b[0], b[1], b[2], b[3]);
-      }
+    for (int k = 0; k < MAXK; ++k) {
+      const int kk = 64 * k < g.n ? k : 0;
+      const float* b = buf + (r0 + RSTEP * kk) * P + w4;
+      *reinterpret_cast<float4*>(dp + kk * RSTEP * inner) = make_float4(b[0], b[1], b[2], b[3]);
+    }
   }
 };
 
@@ -558,16 +559,16 @@ struct XTileIO {
   __device__ __forceinline__ static void store(const Geom& g, const TileRef& tr, const float* buf,
                                                float* dst) {
     const int sh = vshift(g);
+    const int nv = g.spt << sh;
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) {
-      const int q = threadIdx.x + 512 * k, s = q >> sh;
-      if (s < g.spt) {
-        int go, lo;
-        coords(g, s, q & ((1 << sh) - 1), go, lo);
-        const float* b = buf + lo;
-        *reinterpret_cast<float4*>(dst + s * g.total + tr.base + go) =
-            make_float4(b[0], b[P], b[2 * P], b[3 * P]);
-      }
+      // straight-line stores (vectors past the tile store the first block again)
+      const int q = threadIdx.x + (512 * k < nv ? 512 * k : 0), s = q >> sh;
+      int go, lo;
+      coords(g, s, q & ((1 << sh) - 1), go, lo);
+      const float* b = buf + lo;
+      *reinterpret_cast<float4*>(dst + s * g.total + tr.base + go) =
+          make_float4(b[0], b[P], b[2 * P], b[3 * P]);
     }
   }
 };
@@ -582,8 +583,10 @@ struct TilePipe {
   using IO = typename std::conditional<XAX && std::is_same<T, float>::value, XTileIO<W>,
                                        TileIO<T, W>>::type;
   float4 v[XAX ? W / 4 : 4];
+  // Past the last tile the last one is loaded again (unused), so that every
+  // iteration issues the same loads and the compiler's wait counts stay exact.
   __device__ __forceinline__ void issue(const Geom& g, long long tile, const T* src) {
-    if (FAST && tile < g.ntiles) IO::issue(g, tile_ref(g, tile), src, v);
+    if (FAST) IO::issue(g, tile_ref(g, tile < g.ntiles ? tile : g.ntiles - 1), src, v);
   }
   __device__ __forceinline__ void commit(const Geom& g, long long tile, const T* src, T* buf) {
     if (FAST)
@@ -603,83 +606,83 @@ __device__ __forceinline__ void tile_store(const Geom& g, long long tile, const 
     store_tile_fast(g, tile, buf, dst, g.spt);
 }
 
-// Arrays a forward stage reads for one strided FP32 tile (L-table plans),
-// loaded ahead of the forward transform in the thread layout of
-// TileIO<float, 32>: L, then r1, r2 =
-//   stage 0: u_hat, -;  stage 1: u_hat, acc;  stage 2: acc, c_tilde;  stage 3: acc, -.
+// Arrays a forward stage reads for one strided FP32 tile of n = 256 rows,
+// loaded one tile ahead in the thread layout of TileIO<float, 32>:
+//   r1, r2 = stage 0: u_hat, -;  1: u_hat, acc;  2: acc, c_tilde;  3: acc, -
+// and L when the plan reads an L table.
 template <int MODE>
 struct StageLoads {
   float4 L[4], r1[4], r2[4];
-  __device__ __forceinline__ void issue(const StageArgs<float>& a, const TileRef& tr,
-                                        long long tile, const float* lam_lds) {
+  __device__ __forceinline__ void issue(const StageArgs<float>& a, long long tile) {
     using IO = TileIO<float, 32>;
-    const Geom& g = a.g;
-    const long long inner = g.inner;
+    const TileRef tr = tile_ref(a.g, tile);
+    const long long inner = a.g.inner;
     const long long i0 = tr.base + IO::row0() * inner + IO::lane4();
     const float* p1 = MODE <= 1 ? a.uhat : a.acc;
     const float* p2 = MODE == 1 ? a.acc : a.ctil;
 #pragma unroll
     for (int k = 0; k < IO::MAXK; ++k) {
-      const long long i = i0 + (64 * k < g.n ? k : 0) * IO::RSTEP * inner;
+      const long long i = i0 + k * IO::RSTEP * inner;
       if (!a.lfly) L[k] = *reinterpret_cast<const float4*>(a.ltab + i);
       r1[k] = *reinterpret_cast<const float4*>(p1 + i);
       if (MODE == 1 || MODE == 2) r2[k] = *reinterpret_cast<const float4*>(p2 + i);
     }
-    if (a.lfly) {
-      // L = kt_s Lambda^ha_s from the eigenvalue tables in LDS: [n0] x, [n1] y,
-      // then the transformed (last) axis. The last axis has one outer block
-      // per species.
-      const long long o = tile / g.tpo;
-      const int s = (int)o;
-      const int ib = (int)(tile - o * g.tpo) * 32 + IO::lane4();
-      const int n0 = (int)a.n0, n1 = (int)a.n1;
-      const bool three = a.n2 > 1;
-      const float* lz = lam_lds + n0 + (three ? n1 : 0);
-      // the four lanes of a vector share y (n0 is a multiple of 4)
-      const int y = three ? ib / n0 : 0;
-      const float* lx = lam_lds + (three ? ib - y * n0 : ib);
-      const float ly = three ? lam_lds[n0 + y] : 0.f;
-      float lxy[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) lxy[e] = lx[e] + ly;
-      const float kt = a.kt[s], ha = a.ha[s];
-#pragma unroll
-      for (int k = 0; k < IO::MAXK; ++k) {
-        const float lr = lz[IO::row0() + 64 * (64 * k < g.n ? k : 0)];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          // Lambda >= the smallest nonzero eigenvalue, far from denormals:
-          // the hardware log2 / exp2 (about 1 ulp) suffice
-          const float lam = lxy[e] + lr;
-          vset<float>(L[k], e, lam > 0.f ? kt * __builtin_amdgcn_exp2f(ha * __builtin_amdgcn_logf(lam)) : 0.f);
-        }
-      }
-    }
   }
 };
 
-// Stage combine from preloaded arrays (same arithmetic as combine_vec).
+// Stage combine of one 256-row strided FP32 tile from preloaded arrays (same
+// arithmetic as combine_vec). With a.lfly, L = kt_s Lambda^ha_s is formed
+// from the eigenvalue tables in LDS ([n0] x, [n1] y, then the transformed
+// last axis); the last axis has one outer block per species.
 template <int MODE>
-__device__ __forceinline__ void combine_pre(const StageArgs<float>& a, float* buf,
-                                            const TileRef& tr, const StageLoads<MODE>& ld) {
+__device__ __forceinline__ void combine_pre(const StageArgs<float>& a, float* buf, long long tile,
+                                            const StageLoads<MODE>& ld, const float* lam_lds) {
   using IO = TileIO<float, 32>;
   const Geom& g = a.g;
+  const TileRef tr = tile_ref(g, tile);
   const long long cst = (long long)a.S * g.total;
   const int r0 = IO::row0(), w4 = IO::lane4();
   const long long inner = g.inner;
   const long long i0 = tr.base + r0 * inner + w4;
   const float cs = a.cs, tau = a.tau;
+  float lxy[4], kt = 0.f, ha = 0.f;
+  const float* lz = lam_lds;
+  if (a.lfly) {
+    const long long o = tile / g.tpo;
+    const int s = (int)o;
+    const int ib = (int)(tile - o * g.tpo) * 32 + w4;
+    const int n0 = (int)a.n0, n1 = (int)a.n1;
+    const bool three = a.n2 > 1;
+    lz = lam_lds + n0 + (three ? n1 : 0);
+    // the four lanes of a vector share y (n0 is a multiple of 4)
+    const int y = three ? ib / n0 : 0;
+    const float* lx = lam_lds + (three ? ib - y * n0 : ib);
+    const float ly = three ? lam_lds[n0 + y] : 0.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) lxy[e] = lx[e] + ly;
+    kt = a.kt[s];
+    ha = a.ha[s];
+  }
 #pragma unroll
   for (int k = 0; k < IO::MAXK; ++k) {
-    if (64 * k >= g.n) break;
     const long long i = i0 + k * IO::RSTEP * inner;
     float* cell = buf + (r0 + IO::RSTEP * k) * IO::P + w4;
     const float4 fh = make_float4(cell[0], cell[1], cell[2], cell[3]);
+    const float lr = a.lfly ? lz[r0 + IO::RSTEP * k] : 0.f;
     float4 o0, o1, out;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
+      float L;
+      if (a.lfly) {
+        // Lambda >= the smallest nonzero eigenvalue, far from denormals: the
+        // hardware log2 / exp2 (about 1 ulp) suffice
+        const float lam = lxy[e] + lr;
+        L = lam > 0.f ? kt * __builtin_amdgcn_exp2f(ha * __builtin_amdgcn_logf(lam)) : 0.f;
+      } else {
+        L = vget<float>(ld.L[k], e);
+      }
       float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
-      stage_coefs_L<float>(MODE, vget<float>(ld.L[k], e), tau, c0, c1, c2, c3);
+      stage_coefs_L<float>(MODE, L, tau, c0, c1, c2, c3);
       const float f = vget<float>(fh, e);
       const float x1 = vget<float>(ld.r1[k], e);
       if (MODE == 0) {
@@ -841,8 +844,9 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
   }
 }
 
-// MODE >= 0: the stage is known at compile time and FAST L-table FP32 plans
-// load the stage arrays ahead; MODE < 0 takes a.mode at run time.
+// MODE >= 0 (FAST FP32 plans whose last axis has 256 points, forward
+// stages): the stage arrays of the next tile are loaded while this one is
+// computed. MODE < 0 takes a.mode at run time.
 template <typename T, class XF, int MODE, bool FAST>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -850,39 +854,45 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const T* src = a.src ? a.src : a.P;
   const int S = a.g.spt;
-  constexpr bool PRE = FAST && MODE >= 0 && std::is_same<T, float>::value && XF::W == 32;
-  // eigenvalue tables for L formed in the kernel
-  float* lam_lds = reinterpret_cast<float*>(smem_raw + a.lam_off);
-  if (PRE && a.lfly) {
-    const int nx = (int)a.n0, ny = (int)a.n1, nz = a.n2 > 1 ? (int)a.n2 : 0;
-    for (int i = threadIdx.x; i < nx + ny + nz; i += blockDim.x)
-      lam_lds[i] = float(i < nx ? a.lam[0][i] : (i < nx + ny ? a.lam[1][i - nx] : a.lam[2][i - nx - ny]));
-    __syncthreads();
-  }
   TilePipe<T, XF::W, FAST, false> pipe;
   pipe.issue(a.g, blockIdx.x, src);
-  for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pipe.commit(a.g, tile, src, buf);
-    __syncthreads();
-    if constexpr (PRE) {
-      const TileRef tr = tile_ref(a.g, tile);
-      const bool pre = (a.ltab || a.lfly) && S == 1 && !a.src;
-      StageLoads<(PRE ? MODE : 0)> ld;
-      if (pre) ld.issue(a, tr, tile, lam_lds);
-      xf(buf, S);
-      if (pre)
-        combine_pre(a, buf, tr, ld);
-      else
-        combine_tile<T, XF::W, FAST>(a, buf, tile);
-    } else {
+  if constexpr (FAST && MODE >= 0 && std::is_same<T, float>::value && XF::W == 32) {
+    // eigenvalue tables for L formed in the kernel
+    float* lam_lds = reinterpret_cast<float*>(smem_raw + a.lam_off);
+    if (a.lfly) {
+      const int nx = (int)a.n0, ny = (int)a.n1, nz = a.n2 > 1 ? (int)a.n2 : 0;
+      for (int i = threadIdx.x; i < nx + ny + nz; i += blockDim.x)
+        lam_lds[i] = float(i < nx ? a.lam[0][i]
+                                  : (i < nx + ny ? a.lam[1][i - nx] : a.lam[2][i - nx - ny]));
+    }
+    StageLoads<MODE> ld;
+    ld.issue(a, blockIdx.x);
+    const long long last = a.g.ntiles - 1;
+    for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
+      const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+      pipe.commit(a.g, tile, src, buf);
+      __syncthreads();
+      pipe.issue(a.g, next, src);
+      xf(buf, 1);
+      combine_pre<MODE>(a, buf, tile, ld, lam_lds);
+      ld.issue(a, next);
+      __syncthreads();
+      xf(buf, 1);
+      tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
+      __syncthreads();
+    }
+  } else {
+    for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
+      pipe.commit(a.g, tile, src, buf);
+      __syncthreads();
+      pipe.issue(a.g, tile + gridDim.x, src);
       if (!a.src) xf(buf, S);
       combine_tile<T, XF::W, FAST>(a, buf, tile);
+      __syncthreads();
+      xf(buf, S);
+      tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
+      __syncthreads();
     }
-    __syncthreads();
-    pipe.issue(a.g, tile + gridDim.x, src);
-    xf(buf, S);
-    tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
-    __syncthreads();
   }
 }
 

@@ -637,8 +637,15 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat)
   a.st_fhat = st_fhat;
   const long long pk = prof_start(p, KC_Z);
   if (p->use_m[ax])
-    launch_zstage_m<T>(use_fast<T>(p, ax, {p->P, src}), mode, dim3(p->grid_m[ax]), p->lds_m[ax],
-                       p->stream, a, p->mfax[ax]);
+    {
+      const bool fast = use_fast<T>(p, ax, {p->P, src});
+      // the per-stage kernels: forward stages of 256-point last axes, L formed
+      // in the kernel or read from the table
+      const bool staged = fast && p->n[ax] == 256 && mode >= 0 && mode <= 3 && !src &&
+                          (p->lfly || p->ltab);
+      launch_zstage_m<T>(fast, staged ? mode : -1, dim3(p->grid_m[ax]), p->lds_m[ax], p->stream,
+                         a, p->mfax[ax]);
+    }
   else
     hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
                        p->stream, a);
