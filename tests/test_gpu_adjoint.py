@@ -8,7 +8,7 @@ import workloads as W
 from oracle import problem
 from paper_2003_13569_amd.torch_api import SFRDEFunction
 from tests.gpu_util import TD, plan_for
-from tests.test_gpu_parity import CASES
+from tests.test_gpu_parity import CASES, VEC_CASES
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +54,18 @@ def test_fp64_adjoint_matches_oracle(wl, scheme):
 def test_fp32_adjoint_matches_oracle(wl):
     u0 = W.initial_fields(wl)
     wbar = np.random.default_rng(12).standard_normal(u0.shape)
+    ref = problem.gradients(wl, u0, M, wbar)
+    got = _gpu_grads(wl, u0, wbar, "f32")
+    assert _rel(got["u0"], ref["u0"]) <= 1e-4
+    for key in ("kappa", "alpha", "params"):
+        r, g = ref[key], got[key]
+        assert np.max(np.abs(g - r)) <= 1e-3 * max(np.max(np.abs(r)), 1e-300), (key, g, r)
+
+
+@pytest.mark.parametrize("wl", [VEC_CASES[0], VEC_CASES[2]], ids=["sch3d-neu-vec", "gm2d-neu-vec"])
+def test_fp32_adjoint_vector_paths_match_oracle(wl):
+    u0 = W.initial_fields(wl)
+    wbar = np.random.default_rng(13).standard_normal(u0.shape)
     ref = problem.gradients(wl, u0, M, wbar)
     got = _gpu_grads(wl, u0, wbar, "f32")
     assert _rel(got["u0"], ref["u0"]) <= 1e-4

@@ -46,6 +46,19 @@ CASES = [
 ]
 IDS = [c.name for c in CASES]
 
+# Shapes that take the FP32 vector tile paths: x tiles of 32 lines with
+# n_x in {64, 128, 256}; strided axes with 32-lane tiles and 64 | n; the
+# per-stage Z kernels (last axis of 256 points, L formed in the kernel).
+VEC_CASES = [
+    _wl("sch3d-neu-vec", "neumann", (256, 32, 64), "schnakenberg", SCH, (1.5, 1.2), (0.05, 1.0),
+        0.005, "schnak_noise", (0.0, 1.0)),
+    _wl("sch3d-dir-vec", "dirichlet", (64, 64, 128), "schnakenberg", SCH, (1.8, 1.8),
+        (0.05, 1.0), 0.01, "schnak_noise", (0.0, 1.0)),
+    _wl("gm2d-neu-vec", "neumann", (256, 128), "gierer_meinhardt", GM, (1.6, 1.4), (1e-3, 0.05),
+        0.05, "gm_noise", (0.0, 2.0)),
+]
+VEC_IDS = [c.name for c in VEC_CASES]
+
 
 @pytest.mark.parametrize("scheme", ["p13", "exp"])
 @pytest.mark.parametrize("wl", CASES, ids=IDS)
@@ -59,6 +72,16 @@ def test_fp64_matches_oracle(wl, scheme):
 
 @pytest.mark.parametrize("wl", CASES, ids=IDS)
 def test_fp32_matches_oracle(wl):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 5)
+    got = run(wl, u0, 5, "f32")
+    assert problem.rel_err(got, ref) <= 2e-5
+
+
+@pytest.mark.parametrize("scheme", ["p13", "exp"])
+@pytest.mark.parametrize("wl", VEC_CASES, ids=VEC_IDS)
+def test_fp32_vector_paths_match_oracle(wl, scheme):
+    wl = wl.replace(scheme=scheme)
     u0 = W.initial_fields(wl)
     ref = problem.run(wl, u0, 5)
     got = run(wl, u0, 5, "f32")
