@@ -416,6 +416,8 @@ struct StageArgs {
   T ha[MAX_SPECIES];  // alpha_s / 2
   int lfly;
   int lam_off;        // byte offset of the eigenvalue tables in dynamic LDS
+  double* thp;        // adjoint Z kernels on L formed in the kernel: per-block kappa and
+                      // alpha gradient partials [2 S][gridDim.x], accumulated (else G)
   int S;
   int mode;         // stage 0..3, or MODE_INIT / MODE_RESTORE
   int last;         // adjoint: this is step 0 (output u-bar, not phi3 u-bar)

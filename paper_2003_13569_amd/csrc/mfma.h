@@ -573,6 +573,64 @@ struct XTileIO {
   }
 };
 
+// Adjoint reaction on an x tile in the XTileIO layout (every thread takes 4
+// consecutive points of a line, all species): the stored stage values are
+// read as vectors and the Neumann point weights formed from the coordinates.
+template <int NS>
+__device__ __forceinline__ void xadj_reaction_vec(const StageArgs<float>& a, float* buf,
+                                                  long long tile, double* pacc) {
+  using IO = XTileIO<32>;
+  const Geom& g = a.g;
+  const TileRef tr = tile_ref(g, tile);
+  const bool want_p = a.rp_acc != nullptr;
+  const int sh = IO::vshift(g);  // vectors per species 2^sh
+  const int n = g.n;
+  const long long line0 = tile * 32;
+  const int n1 = (int)a.n1;
+  const bool three = a.n2 > 1;
+  const int nv = 1 << sh;
+#pragma unroll 1
+  for (int q = threadIdx.x; q < nv; q += 512) {
+    int go, lo;
+    IO::coords(g, 0, q, go, lo);
+    const int line = go / n, j = go - line * n;
+    const long long idx = tr.base + go;
+    float4 u4[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      u4[s] = *reinterpret_cast<const float4*>(a.st_phys + ((long long)a.mode * NS + s) * g.total + idx);
+    double wl = 1.0;
+    if (a.neumann) {
+      const long long gl = line0 + line;  // line index = y + n1 z
+      const int y = (int)(gl % n1), z = three ? (int)(gl / n1) : 0;
+      if (y == 0 || y == n1 - 1) wl *= 0.5;
+      if (three && (z == 0 || z == (int)a.n2 - 1)) wl *= 0.5;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float u[NS], gg[NS], o[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        u[s] = vget<float>(u4[s], e);
+        gg[s] = buf[lo + s * n * IO::P + e * IO::P];
+      }
+      const double w = a.neumann && (j + e == 0 || j + e == n - 1) ? 0.5 * wl : wl;
+      rxn_adjoint<float, NS>(a.rxn, u, gg, o, w, pacc, want_p);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) buf[lo + s * n * IO::P + e * IO::P] = o[s];
+    }
+  }
+}
+
+__device__ __forceinline__ void xadj_reaction_fast(const StageArgs<float>& a, float* buf,
+                                                   long long tile, double* pacc) {
+  switch (a.S) {
+    case 1: xadj_reaction_vec<1>(a, buf, tile, pacc); break;
+    case 2: xadj_reaction_vec<2>(a, buf, tile, pacc); break;
+    default: pw_adj_reaction(a, buf, tile, pacc); break;
+  }
+}
+
 // Register prefetch of a tile. FAST kernels (chosen by the host when every
 // tile is full, the shapes fit the layouts above and the pointers are
 // 16-byte aligned) move tiles with TileIO only; the others with the generic
@@ -713,6 +771,196 @@ __device__ __forceinline__ void combine_pre(const StageArgs<float>& a, float* bu
     cell[1] = out.y;
     cell[2] = out.z;
     cell[3] = out.w;
+  }
+}
+
+// All six P13 coefficients of L (order C_R, C_Q, C_PHI, C_PHI1, C_PHI2,
+// C_PHI3) and, for the parameter gradients, their derivatives in L from the
+// quotient rule, g' = (num' - g den') / den, with D' = 18 + 12L + 3L^2 and
+// Dh' = 72 + 24L + 3L^2 (Section 4's rational forms).
+__device__ __forceinline__ void p13_all(float L, float tau, float* c) {
+  const float D = 24.f + L * (18.f + L * (6.f + L));
+  const float Dh = 192.f + L * (72.f + L * (12.f + L));
+  const float iD = __builtin_amdgcn_rcpf(D), iDh = __builtin_amdgcn_rcpf(Dh);
+  const bool small = L < 1.f;
+  const float ph = 96.f + L * (12.f + L);
+  c[C_R] = small ? 1.f - L * (24.f + L * (6.f + L)) * iD : (24.f - 6.f * L) * iD;
+  c[C_Q] = small ? 1.f - L * ph * iDh : 24.f * (8.f - L) * iDh;
+  c[C_PHI] = tau * ph * iDh;
+  c[C_PHI1] = tau * (4.f - L) * iD;
+  c[C_PHI2] = 2.f * tau * (4.f + L) * iD;
+  c[C_PHI3] = tau * (4.f + L * (3.f + L)) * iD;
+}
+__device__ __forceinline__ void p13_dall(float L, float tau, const float* c, float* d) {
+  const float D = 24.f + L * (18.f + L * (6.f + L));
+  const float Dh = 192.f + L * (72.f + L * (12.f + L));
+  const float iD = __builtin_amdgcn_rcpf(D), iDh = __builtin_amdgcn_rcpf(Dh);
+  const float dD = 18.f + L * (12.f + 3.f * L), dDh = 72.f + L * (24.f + 3.f * L);
+  d[C_R] = (-6.f - c[C_R] * dD) * iD;
+  d[C_Q] = (-24.f - c[C_Q] * dDh) * iDh;
+  d[C_PHI] = (tau * (12.f + 2.f * L) - c[C_PHI] * dDh) * iDh;
+  d[C_PHI1] = (-tau - c[C_PHI1] * dD) * iD;
+  d[C_PHI2] = (2.f * tau - c[C_PHI2] * dD) * iD;
+  d[C_PHI3] = (tau * (3.f + 2.f * L) - c[C_PHI3] * dD) * iD;
+}
+
+// Adjoint combine (same arithmetic as pw_adj_combine, MODE 0..3 or
+// MODE_INIT) on a one-species strided FP32 tile, L formed from the LDS
+// eigenvalue tables. With TH, each coefficient application's
+// y g'(L) x (the G increment) is turned into the kappa and alpha gradient
+// contributions at once: times the spectral weight, then by dL/dkappa =
+// tau Lambda^(alpha/2) and dL/dalpha = L ln(Lambda) / 2, summed per thread
+// in FP64 (acc[2s], acc[2s + 1]).
+template <int MODE, bool TH>
+__device__ __forceinline__ void zadj_tile32(const StageArgs<float>& a, float* buf, long long tile,
+                                            const float* lam_lds, double (&acc)[4]) {
+  using IO = TileIO<float, 32>;
+  const Geom& g = a.g;
+  const TileRef tr = tile_ref(g, tile);
+  const long long cst = (long long)a.S * g.total;
+  const int r0 = IO::row0(), w4 = IO::lane4();
+  const long long inner = g.inner;
+  const long long i0 = tr.base + r0 * inner + w4;
+  const float cs = a.cs, tau = a.tau;
+  const long long o = tile / g.tpo;
+  const int s = (int)o;
+  const int ib = (int)(tile - o * g.tpo) * 32 + w4;
+  const int n0 = (int)a.n0, n1 = (int)a.n1;
+  const bool three = a.n2 > 1;
+  const float* lz = lam_lds + n0 + (three ? n1 : 0);
+  const int y = three ? ib / n0 : 0;
+  const int x0 = three ? ib - y * n0 : ib;
+  const float* lx = lam_lds + x0;
+  const float ly = three ? lam_lds[n0 + y] : 0.f;
+  // spectral weights: cs times the Neumann end weights
+  float wxy[4];
+  {
+    const bool neu = a.neumann;
+    const float wy = (neu && three && (y == 0 || y == n1 - 1)) ? 0.5f : 1.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      wxy[e] = cs * wy * ((neu && (x0 + e == 0 || x0 + e == n0 - 1)) ? 0.5f : 1.f);
+  }
+  const float kt = a.kt[s], ha = a.ha[s];
+  double acc_k = 0.0, acc_a = 0.0;
+#pragma unroll
+  for (int k = 0; k < IO::MAXK; ++k) {
+    if (64 * k >= g.n) break;
+    const int row = r0 + IO::RSTEP * k;
+    const long long i = i0 + k * IO::RSTEP * inner;
+    float* cell = buf + row * IO::P + w4;
+    const float4 Xv = make_float4(cell[0], cell[1], cell[2], cell[3]);
+    float4 z4, a4, h4, u4, gu4, f0, f1, f2, f3;
+    if (MODE == 0 || MODE == 1) z4 = *reinterpret_cast<const float4*>(a.zh + i);
+    if (MODE == 1 || MODE == 2 || MODE == 3) a4 = *reinterpret_cast<const float4*>(a.aacc + i);
+    if (MODE == 2) {
+      h4 = *reinterpret_cast<const float4*>(a.ahat + i);
+      gu4 = *reinterpret_cast<const float4*>(a.gu + i);
+    }
+    if (TH && MODE <= 2) {
+      u4 = *reinterpret_cast<const float4*>(a.st_uhat + i);
+      if (MODE == 0 || MODE == 2) f0 = *reinterpret_cast<const float4*>(a.st_fhat + i);
+      if (MODE == 0 || MODE == 1) f1 = *reinterpret_cast<const float4*>(a.st_fhat + cst + i);
+      if (MODE == 0) {
+        f2 = *reinterpret_cast<const float4*>(a.st_fhat + 2 * cst + i);
+        f3 = *reinterpret_cast<const float4*>(a.st_fhat + 3 * cst + i);
+      }
+    }
+    const float lr = lz[row];
+    const float wz = (a.neumann && (row == 0 || row == g.n - 1)) ? 0.5f : 1.f;
+    float4 out, o1, o2, o3;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float lam = lx[e] + ly + lr;
+      const float pw = lam > 0.f ? __builtin_amdgcn_exp2f(ha * __builtin_amdgcn_logf(lam)) : 0.f;
+      const float L = kt * pw;
+      float c[NCOEF];
+      p13_all(L, tau, c);
+      const float X = vget<float>(Xv, e);
+      float ov = 0.f, gsum = 0.f;
+      if (MODE == 0) {
+        const float z = vget<float>(z4, e);
+        vset<float>(o1, e, c[C_R] * z);
+        vset<float>(o2, e, c[C_Q] * X);
+        vset<float>(o3, e, c[C_PHI1] * z - c[C_PHI] * X);
+        ov = c[C_PHI2] * z + 2.f * c[C_PHI] * X;
+        if (TH) {
+          float d[NCOEF];
+          p13_dall(L, tau, c, d);
+          const float uh = vget<float>(u4, e), fu = vget<float>(f0, e), fa = vget<float>(f1, e);
+          const float fb = vget<float>(f2, e), fc = vget<float>(f3, e);
+          const float ah = c[C_Q] * uh + c[C_PHI] * fu;
+          const float s1 = d[C_R] * uh + d[C_PHI1] * fu + d[C_PHI2] * (fa + fb) + d[C_PHI3] * fc;
+          const float s2 = d[C_Q] * ah + d[C_PHI] * (2.f * fb - fu);
+          gsum = z * s1 + X * s2;
+        }
+      } else if (MODE == 1) {
+        const float z = vget<float>(z4, e);
+        vset<float>(o1, e, vget<float>(a4, e) + c[C_Q] * X);
+        ov = c[C_PHI2] * z + c[C_PHI] * X;
+        if (TH) {
+          float d[NCOEF];
+          p13_dall(L, tau, c, d);
+          gsum = X * (d[C_Q] * vget<float>(u4, e) + d[C_PHI] * vget<float>(f1, e));
+        }
+      } else if (MODE == 2) {
+        const float A = vget<float>(h4, e) + X;
+        vset<float>(o1, e, vget<float>(a4, e) + c[C_Q] * A);
+        ov = vget<float>(gu4, e) + c[C_PHI] * A;
+        if (TH) {
+          float d[NCOEF];
+          p13_dall(L, tau, c, d);
+          gsum = A * (d[C_Q] * vget<float>(u4, e) + d[C_PHI] * vget<float>(f0, e));
+        }
+      } else if (MODE == 3) {
+        const float zn = vget<float>(a4, e) + X;
+        vset<float>(o1, e, zn);
+        ov = a.last ? zn : c[C_PHI3] * zn;
+      } else {  // MODE_INIT
+        vset<float>(o1, e, X);
+        ov = c[C_PHI3] * X;
+      }
+      vset<float>(out, e, cs * ov);
+      if (TH && MODE <= 2 && lam > 0.f) {
+        const double gw = double(wxy[e] * wz) * double(gsum);
+        acc_k += gw * double(tau * pw);
+        acc_a += gw * (0.5 * double(L) * 0.6931471805599453 * double(__builtin_amdgcn_logf(lam)));
+      }
+    }
+    if (MODE == 0) {
+      *reinterpret_cast<float4*>(a.aacc + i) = o1;
+      *reinterpret_cast<float4*>(a.ahat + i) = o2;
+      *reinterpret_cast<float4*>(a.gu + i) = o3;
+    } else if (MODE == 1 || MODE == 2) {
+      *reinterpret_cast<float4*>(a.aacc + i) = o1;
+    } else {
+      *reinterpret_cast<float4*>(a.zh + i) = o1;
+    }
+    cell[0] = out.x;
+    cell[1] = out.y;
+    cell[2] = out.z;
+    cell[3] = out.w;
+  }
+  if (TH) {
+    if (s == 0) {
+      acc[0] += acc_k;
+      acc[1] += acc_a;
+    } else {
+      acc[2] += acc_k;
+      acc[3] += acc_a;
+    }
+  }
+}
+
+template <bool TH>
+__device__ __forceinline__ void zadj_vec(const StageArgs<float>& a, float* buf, long long tile,
+                                         const float* lam_lds, double (&acc)[4]) {
+  switch (a.mode) {
+    case 0: zadj_tile32<0, TH>(a, buf, tile, lam_lds, acc); break;
+    case 1: zadj_tile32<1, TH>(a, buf, tile, lam_lds, acc); break;
+    case 2: zadj_tile32<2, TH>(a, buf, tile, lam_lds, acc); break;
+    case 3: zadj_tile32<3, false>(a, buf, tile, lam_lds, acc); break;
+    default: zadj_tile32<MODE_INIT, false>(a, buf, tile, lam_lds, acc); break;
   }
 }
 
@@ -910,7 +1158,10 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
     pipe.commit(a.g, tile, a.P, buf);
     __syncthreads();
     xf(buf, S);
-    pw_adj_reaction(a, buf, tile, pacc);
+    if constexpr (FAST && std::is_same<T, float>::value && XF::XAX)
+      xadj_reaction_fast(a, buf, tile, pacc);
+    else
+      pw_adj_reaction(a, buf, tile, pacc);
     __syncthreads();
     pipe.issue(a.g, tile + gridDim.x, a.P);
     xf(buf, S);
@@ -928,6 +1179,49 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
   const int S = a.g.spt;
   TilePipe<T, XF::W, FAST, false> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
+  if constexpr (FAST && std::is_same<T, float>::value && XF::W == 32) {
+    // (a per-point accumulator G, when present, is filled by the generic path)
+    if (a.lfly && S == 1 && (a.thp != nullptr || a.G == nullptr)) {
+      float* lam_lds = reinterpret_cast<float*>(smem_raw + a.lam_off);
+      const int nx = (int)a.n0, ny = (int)a.n1, nz = a.n2 > 1 ? (int)a.n2 : 0;
+      for (int i = threadIdx.x; i < nx + ny + nz; i += blockDim.x)
+        lam_lds[i] = float(i < nx ? a.lam[0][i]
+                                  : (i < nx + ny ? a.lam[1][i - nx] : a.lam[2][i - nx - ny]));
+      // kappa, alpha partials of (at most, host-checked) two species
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      const bool th = a.thp != nullptr;
+      for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
+        pipe.commit(a.g, tile, a.P, buf);
+        __syncthreads();
+        xf(buf, 1);
+        if (th)
+          zadj_vec<true>(a, buf, tile, lam_lds, acc);
+        else
+          zadj_vec<false>(a, buf, tile, lam_lds, acc);
+        __syncthreads();
+        pipe.issue(a.g, tile + gridDim.x, a.P);
+        xf(buf, 1);
+        tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
+        __syncthreads();
+      }
+      if (th) {
+        double* red = reinterpret_cast<double*>(smem_raw);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q >= 2 * a.S) break;
+          red[threadIdx.x] = acc[q];
+          __syncthreads();
+          for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+            __syncthreads();
+          }
+          if (threadIdx.x == 0) a.thp[(long long)q * gridDim.x + blockIdx.x] += red[0];
+          __syncthreads();
+        }
+      }
+      return;
+    }
+  }
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
     pipe.commit(a.g, tile, a.P, buf);
     __syncthreads();

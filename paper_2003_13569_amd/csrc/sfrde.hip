@@ -96,6 +96,8 @@ struct sfrde_plan_s {
   void* dcoef = nullptr;
   void* ltab = nullptr;  // P13 plans: L per species and point
   bool lfly = false;     // FP32 P13 Z kernels form L from the eigenvalues
+  double* thp = nullptr;  // adjoint kappa/alpha partials per Z block [4][grid]
+  bool thp_on = false;    // this backward call accumulates them (else G)
   size_t lam_off = 0;    // LDS byte offset of the eigenvalue tables (last axis kernels)
   void* P = nullptr;
   void* uhat = nullptr;
@@ -794,6 +796,7 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
   a.mode = mode;
   a.last = last;
   a.G = p->G;
+  a.thp = p->thp_on ? p->thp : nullptr;
   if (st) {
     a.st_uhat = st->uhat;
     a.st_fhat = st->fhat;
@@ -846,7 +849,9 @@ int ensure_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_thet
     TRY(dev_alloc(p, &p->seg, (size_t)seg_steps * 9 * f));
     p->seg_steps = seg_steps;
   }
-  if (want_theta) {
+  if (want_theta && p->thp_on) {
+    TRY(dev_alloc(p, (void**)&p->thp, (size_t)4 * p->grid_m[p->ndim - 1] * sizeof(double)));
+  } else if (want_theta) {
     TRY(dev_alloc(p, (void**)&p->G, (size_t)p->S * p->total * sizeof(double)));
     if (!p->dcoef) {
       TRY(dev_alloc(p, &p->dcoef, NCOEF * f));
@@ -894,11 +899,16 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
   const bool want_theta = gk || ga;
   const bool want_p = gp != nullptr && p->rxn.np > 0;
   const long long seg_steps = std::min(K, nsteps);
+  // kappa/alpha gradients formed inside the vector adjoint Z kernels (L
+  // formed there too), else through the per-point accumulator G
+  p->thp_on = want_theta && p->lfly && p->S <= 2 && use_fast<T>(p, p->ndim - 1, {});
   TRY(ensure_backward_buffers(p, seg_steps, want_theta, want_p));
   // Buffers from an earlier call stay allocated; accumulate only what is asked.
   double* G_saved = p->G;
-  if (!want_theta) p->G = nullptr;
+  if (!want_theta || p->thp_on) p->G = nullptr;
   if (p->G) TRY(fill<double>(p, p->G, (long long)p->S * p->total, 0.0));
+  const long long zgrid = p->grid_m[p->ndim - 1];
+  if (p->thp_on) TRY(fill<double>(p, p->thp, 4 * zgrid, 0.0));
   double* rp_saved = p->rp_acc;
   if (!want_p) p->rp_acc = nullptr;
   if (p->rp_acc) TRY(fill<double>(p, p->rp_acc, (long long)MAX_PARAMS * rp_blocks(p), 0.0));
@@ -927,7 +937,16 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
     if (grad_u0 && (rc = launch_single<T>(p, 0, p->Pa, grad_u0, 0, 1))) break;
     const int nb = 1024;
     double host[2 * MAX_SPECIES + MAX_PARAMS];
-    if (want_theta) {
+    if (want_theta && p->thp_on) {
+      hipLaunchKernelGGL(k_rowsum, dim3(2 * p->S), dim3(NTHREADS), 0, p->stream, p->thp, zgrid,
+                         p->red + 2 * MAX_SPECIES * 1024);
+      if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
+      if (hipMemcpyAsync(host, p->red + 2 * MAX_SPECIES * 1024, 2 * p->S * sizeof(double),
+                         hipMemcpyDeviceToHost, p->stream) != hipSuccess) {
+        rc = fail(SFRDE_EDEVICE, "copy of gradient partials");
+        break;
+      }
+    } else if (want_theta) {
       CoefArgs c{};
       c.lam0 = p->lam[0];
       c.lam1 = p->lam[1];
@@ -978,6 +997,7 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
   } while (0);
   p->G = G_saved;
   p->rp_acc = rp_saved;
+  p->thp_on = false;
   return rc;
 }
 
@@ -987,7 +1007,7 @@ void destroy_plan(sfrde_plan_s* p) {
   void** ptrs[] = {&p->Mt[0], &p->Mt[1], &p->Mt[2], (void**)&p->lam[0], (void**)&p->lam[1],
                    (void**)&p->lam[2], &p->coef, &p->dcoef, &p->ltab, &p->P, &p->uhat, &p->ctil, &p->acc,
                    &p->Pa, &p->zh, &p->aacc, &p->ahat, &p->gu, (void**)&p->G, &p->seg,
-                   (void**)&p->rp_acc, (void**)&p->red, (void**)&p->flag, &p->mf_A[0],
+                   (void**)&p->rp_acc, (void**)&p->thp, (void**)&p->red, (void**)&p->flag, &p->mf_A[0],
                    &p->mf_A[1], &p->mf_A[2]};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
