@@ -60,6 +60,78 @@ def bytes_per_point_step(ndim: int, S: int, w: int) -> float:
     return float(S * w * (16 * (ndim - 1) + 11))
 
 
+KERNEL_CLASSES = (("k_zstage", "Z"), ("k_xstage", "X"), ("k_single", "Y"), ("k_zadj", "ZADJ"),
+                  ("k_xadj", "XADJ"))
+
+
+def kernel_class(name: str):
+    base = name.split("(")[0]
+    for key, cls in KERNEL_CLASSES:
+        if ("sfrde::" + key + "_m<") in base or ("sfrde::" + key + "<") in base:
+            return cls
+    return None
+
+
+def _pmc_per_dispatch(path: str, counter: str):
+    """Counter value (KiB) of every dispatch in a rocprofv3 counter CSV: [(name, value)]."""
+    import csv
+    out = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def summarize_pmc(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, out_json, workload):
+    """HBM bytes per launch for each kernel class from FETCH_SIZE / WRITE_SIZE.
+
+    Each counter is scaled by what it reads for a plain device copy of known
+    size (bench.py --copy-calibration: 1 GiB read and 1 GiB written per copy;
+    the largest dispatches of that run are the copies).
+    """
+    nb = float(1 << 30)
+    cf = sorted(v for _, v in _pmc_per_dispatch(copy_fetch_csv, "FETCH_SIZE"))[-1]
+    cw = sorted(v for _, v in _pmc_per_dispatch(copy_write_csv, "WRITE_SIZE"))[-1]
+    f_scale, w_scale = nb / (cf * 1024.0), nb / (cw * 1024.0)
+    res = {}
+    for counter, path, scale in (("fetch", fetch_csv, f_scale), ("write", write_csv, w_scale)):
+        name = "FETCH_SIZE" if counter == "fetch" else "WRITE_SIZE"
+        for kname, v in _pmc_per_dispatch(path, name):
+            cls = kernel_class(kname)
+            if cls is None:
+                continue
+            d = res.setdefault(cls, {"fetch": [], "write": []})
+            d[counter].append(v * 1024.0 * scale)
+    summary = {"workload": workload, "src_hash": src_hash(), "fetch_scale": round(f_scale, 4),
+               "write_scale": round(w_scale, 4), "classes": {}}
+    for cls, d in res.items():
+        fb = sum(d["fetch"]) / max(len(d["fetch"]), 1)
+        wb = sum(d["write"]) / max(len(d["write"]), 1)
+        summary["classes"][cls] = {"launches": len(d["fetch"]), "fetch_bytes": round(fb),
+                                   "write_bytes": round(wb), "hbm_bytes_per_launch": round(fb + wb)}
+    with open(out_json, "w") as fh:
+        json.dump(summary, fh, indent=1)
+    print(json.dumps(summary, indent=1))
+
+
+def summarize_stats(stats_csv):
+    """Markdown table of a rocprofv3 --stats kernel summary, grouped by class."""
+    import csv
+    rows = []
+    with open(stats_csv) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]),
+                         float(r["AverageNs"]), float(r["Percentage"])))
+    rows.sort(key=lambda r: -r[2])
+    print("| Kernel | Class | Calls | Avg (ms) | Total (ms) | Share |")
+    print("|---|---|---|---|---|---|")
+    for name, calls, tot, avg, pct in rows:
+        short = name.split("(")[0].replace("sfrde::", "")
+        print(f"| `{short}` | {kernel_class(name) or '-'} | {calls} | {avg / 1e6:.4f} | "
+              f"{tot / 1e6:.3f} | {pct:.1f} % |")
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,7 +146,20 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (PMC scaling)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH",
+                                                          "COPY_WRITE"),
+                    help="rocprofv3 counter CSVs -> per-class HBM bytes per launch (no GPU)")
+    ap.add_argument("--summarize-stats", metavar="KERNEL_STATS_CSV",
+                    help="rocprofv3 --stats CSV -> markdown table (no GPU)")
+    ap.add_argument("--out", help="output JSON of --summarize-pmc")
     args = ap.parse_args()
+
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.out, "schnakenberg3d_neumann_256")
+        return 0
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats)
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -154,14 +239,17 @@ def main() -> int:
     t_dom, n_dom = prof[dom]
     avg_ms = t_dom / n_dom
     achieved = algorithmic_bytes(dom, S, n, w32) / (avg_ms * 1e-3) / 1e9
-    kernel_names = {"X": "k_xstage<float>", "Y": "k_single<float>", "Z": "k_zstage<float>"}
+    kernel_names = {"X": "k_xstage_m<float> (inverse-x, reaction, forward-x)",
+                    "Y": "k_single_m<float> (y transform)",
+                    "Z": "k_zstage_m<float> (forward-z, stage combine, inverse-z; four stage "
+                         "kernels)"}
     traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"traffic_{dom}_{wl.name}_f32.json")
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{wl.name}_f32.json")
     if os.path.exists(tfile):
         with open(tfile) as fh:
             tj = json.load(fh)
-        if tj.get("src_hash") == src_hash():
-            traffic = tj.get("hbm_bytes_per_launch")
+        if tj.get("src_hash") == src_hash() and dom in tj.get("classes", {}):
+            traffic = tj["classes"][dom]["hbm_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kernel_names[dom], "avg_launch_ms": round(avg_ms, 4),
