@@ -1068,28 +1068,35 @@ __device__ __forceinline__ void combine_tile(const StageArgs<T>& a, T* buf, long
 
 // ------------------------------------------------------------------ kernels
 // Persistent: block b handles tiles b, b + gridDim.x, ... The loads of the
-// next tile are issued before the current one is computed (where they do not
-// compete with other loads of the current tile), and the Z kernels' stage
-// arrays before the forward transform.
+// next tile are issued before the current one is computed and written to LDS
+// after its stores: the wait then covers those loads only (the stores just
+// issued stay in flight), on the one path through the loop body. Past the
+// last tile, the last one is loaded again and dropped.
 template <typename T, class XF, bool FAST>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const int S = a.g.spt;
+  const long long last = a.g.ntiles - 1;
   TilePipe<T, XF::W, FAST, true> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
+  pipe.commit(a.g, blockIdx.x, a.P, buf);
+  __syncthreads();
+  bool bad = false;
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pipe.commit(a.g, tile, a.P, buf);
-    __syncthreads();
-    pipe.issue(a.g, tile + gridDim.x, a.P);
+    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+    pipe.issue(a.g, next, a.P);
     xf(buf, S);
-    if (pw_reaction(a, buf, tile)) a.flag[0] = 1;
+    bad |= pw_reaction(a, buf, tile);
     __syncthreads();
     xf(buf, S);
     tile_store<T, XF::W, FAST, true>(a.g, tile, buf, a.P);
     __syncthreads();
+    pipe.commit(a.g, next, a.P, buf);
+    __syncthreads();
   }
+  if (bad) a.flag[0] = 1;
 }
 
 // MODE >= 0 (FAST FP32 plans whose last axis has 256 points, forward
@@ -1102,6 +1109,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const T* src = a.src ? a.src : a.P;
   const int S = a.g.spt;
+  const long long last = a.g.ntiles - 1;
   TilePipe<T, XF::W, FAST, false> pipe;
   pipe.issue(a.g, blockIdx.x, src);
   if constexpr (FAST && MODE >= 0 && std::is_same<T, float>::value && XF::W == 32) {
@@ -1115,11 +1123,10 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
     }
     StageLoads<MODE> ld;
     ld.issue(a, blockIdx.x);
-    const long long last = a.g.ntiles - 1;
+    pipe.commit(a.g, blockIdx.x, src, buf);
+    __syncthreads();
     for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
       const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
-      pipe.commit(a.g, tile, src, buf);
-      __syncthreads();
       pipe.issue(a.g, next, src);
       xf(buf, 1);
       combine_pre<MODE>(a, buf, tile, ld, lam_lds);
@@ -1128,17 +1135,22 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
       xf(buf, 1);
       tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
       __syncthreads();
+      pipe.commit(a.g, next, src, buf);
+      __syncthreads();
     }
   } else {
+    pipe.commit(a.g, blockIdx.x, src, buf);
+    __syncthreads();
     for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-      pipe.commit(a.g, tile, src, buf);
-      __syncthreads();
-      pipe.issue(a.g, tile + gridDim.x, src);
+      const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
       if (!a.src) xf(buf, S);
       combine_tile<T, XF::W, FAST>(a, buf, tile);
       __syncthreads();
+      pipe.issue(a.g, next, src);
       xf(buf, S);
       tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
+      __syncthreads();
+      pipe.commit(a.g, next, src, buf);
       __syncthreads();
     }
   }
@@ -1152,20 +1164,24 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
   double pacc[RXN_NP_MAX];
   for (int k = 0; k < RXN_NP_MAX; ++k) pacc[k] = 0.0;
   const int S = a.g.spt;
+  const long long last = a.g.ntiles - 1;
   TilePipe<T, XF::W, FAST, true> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
+  pipe.commit(a.g, blockIdx.x, a.P, buf);
+  __syncthreads();
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pipe.commit(a.g, tile, a.P, buf);
-    __syncthreads();
+    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
     xf(buf, S);
     if constexpr (FAST && std::is_same<T, float>::value && XF::XAX)
       xadj_reaction_fast(a, buf, tile, pacc);
     else
       pw_adj_reaction(a, buf, tile, pacc);
     __syncthreads();
-    pipe.issue(a.g, tile + gridDim.x, a.P);
+    pipe.issue(a.g, next, a.P);
     xf(buf, S);
     tile_store<T, XF::W, FAST, true>(a.g, tile, buf, a.P);
+    __syncthreads();
+    pipe.commit(a.g, next, a.P, buf);
     __syncthreads();
   }
   if (a.rp_acc) block_add_partials(reinterpret_cast<double*>(smem_raw), pacc, a.rxn.np, a.rp_acc);
@@ -1177,8 +1193,10 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const int S = a.g.spt;
+  const long long last = a.g.ntiles - 1;
   TilePipe<T, XF::W, FAST, false> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
+  pipe.commit(a.g, blockIdx.x, a.P, buf);
   if constexpr (FAST && std::is_same<T, float>::value && XF::W == 32) {
     // (a per-point accumulator G, when present, is filled by the generic path)
     if (a.lfly && S == 1 && (a.thp != nullptr || a.G == nullptr)) {
@@ -1187,21 +1205,23 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
       for (int i = threadIdx.x; i < nx + ny + nz; i += blockDim.x)
         lam_lds[i] = float(i < nx ? a.lam[0][i]
                                   : (i < nx + ny ? a.lam[1][i - nx] : a.lam[2][i - nx - ny]));
+      __syncthreads();
       // kappa, alpha partials of (at most, host-checked) two species
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       const bool th = a.thp != nullptr;
       for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-        pipe.commit(a.g, tile, a.P, buf);
-        __syncthreads();
+        const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
         xf(buf, 1);
         if (th)
           zadj_vec<true>(a, buf, tile, lam_lds, acc);
         else
           zadj_vec<false>(a, buf, tile, lam_lds, acc);
         __syncthreads();
-        pipe.issue(a.g, tile + gridDim.x, a.P);
+        pipe.issue(a.g, next, a.P);
         xf(buf, 1);
         tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
+        __syncthreads();
+        pipe.commit(a.g, next, a.P, buf);
         __syncthreads();
       }
       if (th) {
@@ -1222,15 +1242,17 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
       return;
     }
   }
+  __syncthreads();
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    pipe.commit(a.g, tile, a.P, buf);
-    __syncthreads();
+    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
     xf(buf, S);
     pw_adj_combine(a, buf, tile);
     __syncthreads();
-    pipe.issue(a.g, tile + gridDim.x, a.P);
+    pipe.issue(a.g, next, a.P);
     xf(buf, S);
     tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
+    __syncthreads();
+    pipe.commit(a.g, next, a.P, buf);
     __syncthreads();
   }
 }
@@ -1244,12 +1266,14 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const Geom& g = a.g;
   const int ne = g.n * g.W;
+  const long long last = g.ntiles - 1;
   TilePipe<T, XF::W, FAST, XF::XAX> pipe;
   pipe.issue(g, blockIdx.x, a.src);
+  pipe.commit(g, blockIdx.x, a.src, buf);
+  __syncthreads();
   for (long long tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
-    pipe.commit(g, tile, a.src, buf);
-    __syncthreads();
-    pipe.issue(g, tile + gridDim.x, a.src);
+    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+    pipe.issue(g, next, a.src);
     const TileRef tr = tile_ref(g, tile);
     if (a.pre_divide_w) {
       for (int e = threadIdx.x; e < ne; e += blockDim.x) {
@@ -1275,6 +1299,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
       __syncthreads();
     }
     tile_store<T, XF::W, FAST, XF::XAX>(g, tile, buf, a.dst);
+    __syncthreads();
+    pipe.commit(g, next, a.src, buf);
     __syncthreads();
   }
 }
