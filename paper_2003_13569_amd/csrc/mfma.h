@@ -1267,6 +1267,34 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
   const Geom& g = a.g;
   const int ne = g.n * g.W;
   const long long last = g.ntiles - 1;
+  if constexpr (FAST && std::is_same<T, float>::value) {
+    if (!a.pre_divide_w && !a.post_multiply_w) {
+      // two tiles in flight: pipes A and B alternate
+      TilePipe<T, XF::W, FAST, XF::XAX> pa, pb;
+      const long long G = gridDim.x;
+      auto nxt = [&](long long t) { return t < last ? t : last; };
+      pa.issue(g, blockIdx.x, a.src);
+      pb.issue(g, nxt(blockIdx.x + G), a.src);
+      pa.commit(g, blockIdx.x, a.src, buf);
+      __syncthreads();
+      for (long long tile = blockIdx.x; tile < g.ntiles; tile += 2 * G) {
+        pa.issue(g, nxt(tile + 2 * G), a.src);
+        xf(buf, g.spt);
+        tile_store<T, XF::W, FAST, XF::XAX>(g, tile, buf, a.dst);
+        __syncthreads();
+        pb.commit(g, nxt(tile + G), a.src, buf);
+        __syncthreads();
+        if (tile + G >= g.ntiles) break;
+        pb.issue(g, nxt(tile + 3 * G), a.src);
+        xf(buf, g.spt);
+        tile_store<T, XF::W, FAST, XF::XAX>(g, tile + G, buf, a.dst);
+        __syncthreads();
+        pa.commit(g, nxt(tile + 2 * G), a.src, buf);
+        __syncthreads();
+      }
+      return;
+    }
+  }
   TilePipe<T, XF::W, FAST, XF::XAX> pipe;
   pipe.issue(g, blockIdx.x, a.src);
   pipe.commit(g, blockIdx.x, a.src, buf);
