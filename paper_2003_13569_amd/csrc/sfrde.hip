@@ -222,7 +222,7 @@ long long pow2_floor(long long x) {
   return p;
 }
 
-void make_geom(sfrde_plan_s* p, int axis) {
+void make_geom(sfrde_plan_s* p, int axis, long long min_tiles = 0) {
   Geom& g = p->geom[axis];
   const long long n = p->n[axis];
   long long inner = 1;
@@ -237,6 +237,13 @@ void make_geom(sfrde_plan_s* p, int axis) {
   long long W = std::min<long long>(64, pow2_floor(std::max<long long>(1, (KMAX * NTHREADS) / n)));
   while (W > 1 && (size_t)p->S * n * (W + 1) * p->w > 65536) W /= 2;
   if (inner > 1) W = std::min<long long>(W, pow2_floor(inner) * (pow2_floor(inner) < inner ? 2 : 1));
+  // Narrower tiles where there are too few lines to fill the device (small
+  // grids, e.g. 2D): the dense kernels run one tile per block.
+  auto tiles_for = [&](long long w) {
+    const long long lines = p->total / n;
+    return inner == 1 ? (lines + w - 1) / w : (p->total / (n * inner)) * ((inner + w - 1) / w);
+  };
+  while (W > 1 && tiles_for(W) < min_tiles) W /= 2;
   g.W = (int)W;
   g.pitch = (int)(W + 1);
   g.wshift = 0;
@@ -1081,6 +1088,7 @@ int build_plan(sfrde_plan_s* p) {
     HIPCHECK(hipMemcpy(p->lam[a], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   size_t lds_max = 0;
+  for (int a = 0; a < p->ndim; ++a) make_geom(p, a, 2LL * p->n_cu);
   for (int a = 0; a < p->ndim; ++a) TRY(setup_mfma_axis(p, a));
   {
     // FP32 P13 plans whose last axis runs the vector Z kernels form L there

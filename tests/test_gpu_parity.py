@@ -88,6 +88,24 @@ def test_fp32_vector_paths_match_oracle(wl, scheme):
     assert problem.rel_err(got, ref) <= 2e-5
 
 
+# Axes whose folded length exceeds the matrix-core limit (n > 256, periodic
+# n >= 256) take the dense LDS kernels, with tiles narrowed to fill the device.
+DENSE_CASES = [
+    _wl("gs2d-per-dense", "periodic", (24, 300), "gray_scott", GS, (1.7, 1.7), (2e-3, 1e-3), 1.0,
+        "gs_square", (-1.0, 1.0)),
+    _wl("sch2d-dir-dense", "dirichlet", (270, 20), "schnakenberg", SCH, (1.8, 1.6), (0.05, 1.0),
+        0.01, "schnak_noise", (0.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+@pytest.mark.parametrize("wl", DENSE_CASES, ids=[c.name for c in DENSE_CASES])
+def test_dense_axes_match_oracle(wl, dtype, tol):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 5)
+    assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
+
+
 def test_linear_reaction_many_species():
     wl = W.Workload(name="lin4", bc="dirichlet", shape=(14, 19), domain=(0.0, 1.0),
                     alpha=(1.2, 1.5, 1.8, 2.0), kappa=(0.01, 0.02, 0.0, 0.05),
