@@ -284,6 +284,37 @@ struct MfmaXfF32 {
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[h][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (nrb == 0) return;
+    if (nrb == 2 && shareB) {
+      // both row blocks read the same fragments: the 2 CB accumulators are
+      // independent, so consecutive products never wait on one another
+      // (same summation order per accumulator as below)
+#pragma unroll
+      for (int ks = 0; ks < MF_KSMAX_F32; ++ks) {
+        if (ks >= KS) break;
+        f16x8 b0[CB], b1[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const int off = 16 * cb * FBP + 32 * ks;
+          b0[cb] = frag(fb + bofs[0] + off);
+          b1[cb] = frag(fb + bofs[0] + off + TS);
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[h][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[h][ks][1], b0[cb], acc[h][cb], 0, 0, 0);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[h][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[h][ks][0], b1[cb], acc[h][cb], 0, 0, 0);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            acc[h][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[h][ks][0], b0[cb], acc[h][cb], 0, 0, 0);
+      }
+    } else {
 #pragma unroll
     for (int ks = 0; ks < MF_KSMAX_F32; ++ks) {
       if (ks >= KS) break;
@@ -304,6 +335,7 @@ struct MfmaXfF32 {
           acc[1][cb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[1][ks][0], b0, acc[1][cb], 0, 0, 0);
         }
       }
+    }
     }
     const int lane = threadIdx.x % 64;
 #pragma unroll
