@@ -433,7 +433,8 @@ struct StageArgs {
 // Walks the LDS tile row by row (lanes w fastest); the global index is only
 // formed when stage values are stored.
 template <typename T, int NS>
-__device__ __forceinline__ bool pw_reaction_n(const StageArgs<T>& a, T* buf, long long tile) {
+__device__ __forceinline__ bool pw_reaction_n(const StageArgs<T>& a, T* buf, long long tile,
+                                              bool record) {
   const Geom& g = a.g;
   const TileRef tr = tile_ref(g, tile);
   const RxnT<T> rx(a.rxn);
@@ -447,7 +448,7 @@ __device__ __forceinline__ bool pw_reaction_n(const StageArgs<T>& a, T* buf, lon
     T u[NS], f[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) u[s] = cell[s * sstride];
-    if (a.st_phys) {
+    if (record) {
       const long long idx = tr.base + (long long)j * tr.rs + (long long)w * tr.cs;
 #pragma unroll
       for (int s = 0; s < NS; ++s) a.st_phys[((long long)a.mode * NS + s) * g.total + idx] = u[s];
@@ -462,17 +463,20 @@ __device__ __forceinline__ bool pw_reaction_n(const StageArgs<T>& a, T* buf, lon
   return bad;
 }
 
+// record: also store the stage values (a.st_phys) from this pass.
 template <typename T>
-__device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long long tile) {
+__device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long long tile,
+                                            bool record = true) {
+  record = record && a.st_phys != nullptr;
   switch (a.S) {
     case 1:
-      return pw_reaction_n<T, 1>(a, buf, tile);
+      return pw_reaction_n<T, 1>(a, buf, tile, record);
     case 2:
-      return pw_reaction_n<T, 2>(a, buf, tile);
+      return pw_reaction_n<T, 2>(a, buf, tile, record);
     case 3:
-      return pw_reaction_n<T, 3>(a, buf, tile);
+      return pw_reaction_n<T, 3>(a, buf, tile, record);
     default:
-      return pw_reaction_n<T, 4>(a, buf, tile);
+      return pw_reaction_n<T, 4>(a, buf, tile, record);
   }
 }
 

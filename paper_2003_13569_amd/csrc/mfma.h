@@ -284,7 +284,7 @@ struct MfmaXfF32 {
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[h][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (nrb == 0) return;
-    if (nrb == 2 && shareB) {
+    if (!XAX && nrb == 2 && shareB) {
       // both row blocks read the same fragments: the 2 CB accumulators are
       // independent, so consecutive products never wait on one another
       // (same summation order per accumulator as below)
@@ -842,10 +842,44 @@ __device__ __forceinline__ void p13_dall(float L, float tau, const float* c, flo
 // y g'(L) x (the G increment) is turned into the kappa and alpha gradient
 // contributions at once: times the spectral weight, then by dL/dkappa =
 // tau Lambda^(alpha/2) and dL/dalpha = L ln(Lambda) / 2, summed per thread
-// in FP64 (acc[2s], acc[2s + 1]).
+// and tile in FP32 and across tiles in FP64 (acc[2s], acc[2s + 1]).
+// Adjoint stage arrays loaded ahead of the forward transform (up to four per
+// stage, in the thread layout of TileIO<float, 32>):
+//   0: z, [u_hat, f_u, f_a];  1: z, aacc, [u_hat, f_a];  2: a_hat, aacc, gu, [u_hat];
+//   3: aacc;  MODE_INIT: none  (bracketed: with the kappa/alpha gradients).
 template <int MODE, bool TH>
+struct AdjLoads {
+  static constexpr int NQ = MODE == 0 ? (TH ? 4 : 1)
+                          : MODE == 1 ? (TH ? 4 : 2)
+                          : MODE == 2 ? (TH ? 4 : 3)
+                          : MODE == 3 ? 1 : 0;
+  float4 q[NQ > 0 ? NQ : 1][4];
+  __device__ __forceinline__ static const float* src(const StageArgs<float>& a, int j) {
+    const long long cst = (long long)a.S * a.g.total;
+    if (MODE == 0) return j == 0 ? a.zh : j == 1 ? a.st_uhat : j == 2 ? a.st_fhat : a.st_fhat + cst;
+    if (MODE == 1) return j == 0 ? a.zh : j == 1 ? a.aacc : j == 2 ? a.st_uhat : a.st_fhat + cst;
+    if (MODE == 2) return j == 0 ? a.ahat : j == 1 ? a.aacc : j == 2 ? a.gu : a.st_uhat;
+    return a.aacc;
+  }
+  __device__ __forceinline__ void issue(const StageArgs<float>& a, long long tile) {
+    using IO = TileIO<float, 32>;
+    const TileRef tr = tile_ref(a.g, tile);
+    const long long inner = a.g.inner;
+    const long long i0 = tr.base + IO::row0() * inner + IO::lane4();
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const float* p = src(a, j);
+#pragma unroll
+      for (int k = 0; k < IO::MAXK; ++k)
+        q[j][k] = *reinterpret_cast<const float4*>(p + i0 + (64 * k < a.g.n ? k : 0) * IO::RSTEP * inner);
+    }
+  }
+};
+
+template <int MODE, bool TH, bool PRE = false>
 __device__ __forceinline__ void zadj_tile32(const StageArgs<float>& a, float* buf, long long tile,
-                                            const float* lam_lds, double (&acc)[4]) {
+                                            const float* lam_lds, double (&acc)[4],
+                                            const AdjLoads<MODE, TH>* ld = nullptr) {
   using IO = TileIO<float, 32>;
   const Geom& g = a.g;
   const TileRef tr = tile_ref(g, tile);
@@ -874,7 +908,8 @@ __device__ __forceinline__ void zadj_tile32(const StageArgs<float>& a, float* bu
       wxy[e] = cs * wy * ((neu && (x0 + e == 0 || x0 + e == n0 - 1)) ? 0.5f : 1.f);
   }
   const float kt = a.kt[s], ha = a.ha[s];
-  double acc_k = 0.0, acc_a = 0.0;
+  // per-tile sums in FP32 (at most 16 terms per thread), added in FP64
+  float acc_k = 0.f, acc_a = 0.f;
 #pragma unroll
   for (int k = 0; k < IO::MAXK; ++k) {
     if (64 * k >= g.n) break;
@@ -883,6 +918,35 @@ __device__ __forceinline__ void zadj_tile32(const StageArgs<float>& a, float* bu
     float* cell = buf + row * IO::P + w4;
     const float4 Xv = make_float4(cell[0], cell[1], cell[2], cell[3]);
     float4 z4, a4, h4, u4, gu4, f0, f1, f2, f3;
+    if constexpr (PRE) {
+      if (MODE == 0) {
+        z4 = ld->q[0][k];
+        if (TH) {
+          u4 = ld->q[TH ? 1 : 0][k];
+          f0 = ld->q[TH ? 2 : 0][k];
+          f1 = ld->q[TH ? 3 : 0][k];
+          f2 = *reinterpret_cast<const float4*>(a.st_fhat + 2 * cst + i);
+          f3 = *reinterpret_cast<const float4*>(a.st_fhat + 3 * cst + i);
+        }
+      } else if (MODE == 1) {
+        z4 = ld->q[0][k];
+        a4 = ld->q[1][k];
+        if (TH) {
+          u4 = ld->q[TH ? 2 : 0][k];
+          f1 = ld->q[TH ? 3 : 0][k];
+        }
+      } else if (MODE == 2) {
+        h4 = ld->q[0][k];
+        a4 = ld->q[1][k];
+        gu4 = ld->q[2][k];
+        if (TH) {
+          u4 = ld->q[TH ? 3 : 0][k];
+          f0 = *reinterpret_cast<const float4*>(a.st_fhat + i);
+        }
+      } else if (MODE == 3) {
+        a4 = ld->q[0][k];
+      }
+    } else {
     if (MODE == 0 || MODE == 1) z4 = *reinterpret_cast<const float4*>(a.zh + i);
     if (MODE == 1 || MODE == 2 || MODE == 3) a4 = *reinterpret_cast<const float4*>(a.aacc + i);
     if (MODE == 2) {
@@ -898,13 +962,15 @@ __device__ __forceinline__ void zadj_tile32(const StageArgs<float>& a, float* bu
         f3 = *reinterpret_cast<const float4*>(a.st_fhat + 3 * cst + i);
       }
     }
+    }
     const float lr = lz[row];
     const float wz = (a.neumann && (row == 0 || row == g.n - 1)) ? 0.5f : 1.f;
     float4 out, o1, o2, o3;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const float lam = lx[e] + ly + lr;
-      const float pw = lam > 0.f ? __builtin_amdgcn_exp2f(ha * __builtin_amdgcn_logf(lam)) : 0.f;
+      const float lg = lam > 0.f ? __builtin_amdgcn_logf(lam) : 0.f;  // log2(Lambda)
+      const float pw = lam > 0.f ? __builtin_amdgcn_exp2f(ha * lg) : 0.f;
       const float L = kt * pw;
       float c[NCOEF];
       p13_all(L, tau, c);
@@ -954,9 +1020,9 @@ __device__ __forceinline__ void zadj_tile32(const StageArgs<float>& a, float* bu
       }
       vset<float>(out, e, cs * ov);
       if (TH && MODE <= 2 && lam > 0.f) {
-        const double gw = double(wxy[e] * wz) * double(gsum);
-        acc_k += gw * double(tau * pw);
-        acc_a += gw * (0.5 * double(L) * 0.6931471805599453 * double(__builtin_amdgcn_logf(lam)));
+        const float gw = wxy[e] * wz * gsum;
+        acc_k += gw * (tau * pw);
+        acc_a += gw * (0.34657359f * L * lg);  // L ln(Lambda) / 2
       }
     }
     if (MODE == 0) {
@@ -975,11 +1041,11 @@ __device__ __forceinline__ void zadj_tile32(const StageArgs<float>& a, float* bu
   }
   if (TH) {
     if (s == 0) {
-      acc[0] += acc_k;
-      acc[1] += acc_a;
+      acc[0] += double(acc_k);
+      acc[1] += double(acc_a);
     } else {
-      acc[2] += acc_k;
-      acc[3] += acc_a;
+      acc[2] += double(acc_k);
+      acc[3] += double(acc_a);
     }
   }
 }
@@ -1120,7 +1186,17 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
     const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
     pipe.issue(a.g, next, a.P);
     xf(buf, S);
-    bad |= pw_reaction(a, buf, tile);
+    if constexpr (FAST && std::is_same<T, float>::value) {
+      // stage values stored for the adjoint as vectors of the tile
+      if (a.st_phys) {
+        XTileIO<XF::W>::store(a.g, tile_ref(a.g, tile), buf,
+                              a.st_phys + (long long)a.mode * S * a.g.total);
+        __syncthreads();
+      }
+      bad |= pw_reaction(a, buf, tile, false);
+    } else {
+      bad |= pw_reaction(a, buf, tile);
+    }
     __syncthreads();
     xf(buf, S);
     tile_store<T, XF::W, FAST, true>(a.g, tile, buf, a.P);
@@ -1219,7 +1295,32 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
   if (a.rp_acc) block_add_partials(reinterpret_cast<double*>(smem_raw), pacc, a.rxn.np, a.rp_acc);
 }
 
-template <typename T, class XF, bool FAST>
+// Adjoint Z stage on one-species strided FP32 tiles with L formed in the
+// kernel and the stage arrays loaded ahead of the forward transform.
+template <class XF, int MODE, bool TH>
+__device__ __forceinline__ void zadj_staged(const StageArgs<float>& a, float* buf, XF& xf,
+                                            TilePipe<float, XF::W, true, false>& pipe,
+                                            const float* lam_lds, double (&acc)[4]) {
+  const long long last = a.g.ntiles - 1;
+  AdjLoads<MODE, TH> ld;
+  for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
+    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+    ld.issue(a, tile);
+    xf(buf, 1);
+    zadj_tile32<MODE, TH, true>(a, buf, tile, lam_lds, acc, &ld);
+    __syncthreads();
+    pipe.issue(a.g, next, a.P);
+    xf(buf, 1);
+    tile_store<float, XF::W, true, false>(a.g, tile, buf, a.P);
+    __syncthreads();
+    pipe.commit(a.g, next, a.P, buf);
+    __syncthreads();
+  }
+}
+
+// MODE >= 0: one kernel per adjoint stage (FAST FP32 plans with L formed in
+// the kernel); MODE < 0 takes a.mode at run time.
+template <typename T, class XF, bool FAST, int MODE = -1>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(StageArgs<T> a, MfmaAxisDev ax) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
@@ -1241,6 +1342,12 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
       // kappa, alpha partials of (at most, host-checked) two species
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
       const bool th = a.thp != nullptr;
+      if constexpr (MODE >= 0) {
+        if (th)
+          zadj_staged<XF, MODE, MODE <= 2>(a, buf, xf, pipe, lam_lds, acc);
+        else
+          zadj_staged<XF, MODE, false>(a, buf, xf, pipe, lam_lds, acc);
+      } else
       for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
         const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
         xf(buf, 1);

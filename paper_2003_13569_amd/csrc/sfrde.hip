@@ -471,6 +471,11 @@ int set_lds_attrs(size_t bytes) {
                           reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 3, true>),
                           reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, true>),
                           reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 0>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 1>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 2>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 3>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, MODE_INIT>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true>)};
     for (const void* f : fast) fns.push_back(f);
@@ -812,7 +817,23 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
   const long long pk = prof_start(p, KC_ZADJ);
   if (p->use_m[ax]) {
     const dim3 grid(p->grid_m[ax]), block(XfZ<T>::THREADS);
-    if (use_fast<T>(p, ax, {p->Pa}))
+    const size_t lds = p->lds_m[ax];
+    const bool fast = use_fast<T>(p, ax, {p->Pa});
+    // per-stage kernels: L formed in the kernel, no per-point accumulator
+    const bool staged = fast && p->lfly && (p->thp_on || !p->G) && mode >= 0 && mode <= MODE_INIT;
+    if constexpr (std::is_same<T, float>::value) {
+      if (staged) {
+        switch (mode) {
+          case 0: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 0>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
+          case 1: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 1>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
+          case 2: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 2>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
+          case 3: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 3>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
+          default: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, MODE_INIT>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
+        }
+        goto zadj_launched;
+      }
+    }
+    if (fast)
       hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, std::is_same<T, float>::value>), grid, block,
                          p->lds_m[ax], p->stream, a, p->mfax[ax]);
     else
@@ -821,6 +842,7 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
   } else
     hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
                        p->stream, a);
+zadj_launched:
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
