@@ -243,72 +243,6 @@ __device__ __forceinline__ void load_tile_fast(const Geom& g, long long tile,
   }
 }
 
-// Register prefetch of a whole tile (persistent kernels): issue() starts the
-// global loads of a tile, commit() writes them into LDS. Tiles that cannot
-// move in vectors, or need more than CH vectors per thread, are loaded by
-// commit() directly.
-template <typename T, int CH>
-struct TilePrefetch {
-  typename Vec16<T>::type r[CH > 0 ? CH : 1];
-  bool ok;
-
-  __device__ __forceinline__ void issue(const Geom& g, long long tile, const T* __restrict__ src,
-                                        int S) {
-    constexpr int VW = Vec16<T>::N;
-    using V = typename Vec16<T>::type;
-    ok = false;
-    if (CH == 0 || tile >= g.ntiles) return;
-    const TileRef tr = tile_ref(g, tile);
-    ok = tile_vectorizable<T>(g, tr, src) && S * g.n * g.W / VW <= CH * (int)blockDim.x;
-    if (!ok) return;
-    const int per_s = g.n * g.W / VW;
-    const int total_v = S * per_s;
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int v = c * blockDim.x + threadIdx.x;
-      if (v < total_v) {
-        const int s = v >= per_s ? (v >= 2 * per_s ? (v >= 3 * per_s ? 3 : 2) : 1) : 0;
-        long long gi;
-        int j, w;
-        vec_coords<T>(g, tr, v - s * per_s, gi, j, w);
-        r[c] = *reinterpret_cast<const V*>(src + s * g.total + gi);
-      }
-    }
-  }
-
-  __device__ __forceinline__ void commit(const Geom& g, long long tile, const T* src, T* buf,
-                                         int S) {
-    constexpr int VW = Vec16<T>::N;
-    if (!ok) {
-      if (CH > 0)
-        load_tile(g, tile, src, buf, S);
-      else
-        load_tile_fast(g, tile, src, buf, S);
-      return;
-    }
-    const TileRef tr = tile_ref(g, tile);
-    const int per_s = g.n * g.W / VW;
-    const int total_v = S * per_s;
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int v = c * blockDim.x + threadIdx.x;
-      if (v < total_v) {
-        const int s = v >= per_s ? (v >= 2 * per_s ? (v >= 3 * per_s ? 3 : 2) : 1) : 0;
-        long long gi;
-        int j, w;
-        vec_coords<T>(g, tr, v - s * per_s, gi, j, w);
-        T* b = buf + s * g.n * g.pitch;
-        for (int e = 0; e < VW; ++e) {
-          if (g.inner == 1)
-            b[(j + e) * g.pitch + w] = vget<T>(r[c], e);
-          else
-            b[j * g.pitch + w + e] = vget<T>(r[c], e);
-        }
-      }
-    }
-  }
-};
-
 template <typename T>
 __device__ __forceinline__ void store_tile_fast(const Geom& g, long long tile, const T* buf,
                                                 T* __restrict__ dst, int S) {
@@ -932,45 +866,6 @@ __device__ __forceinline__ void body_zadj(const StageArgs<T>& a, T* buf, long lo
   __syncthreads();
   xf(buf, a.g.spt);
   tile_out<FAST>(a.g, tile, buf, a.P, a.g.spt);
-}
-
-// Bodies for tiles already staged in LDS (persistent kernels load ahead).
-template <typename T, class XF>
-__device__ __forceinline__ void run_x(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
-  xf(buf, a.g.spt);
-  const bool bad = pw_reaction(a, buf, tile);
-  if (bad) a.flag[0] = 1;
-  __syncthreads();
-  xf(buf, a.g.spt);
-  store_tile_fast(a.g, tile, buf, a.P, a.g.spt);
-}
-
-template <typename T, class XF>
-__device__ __forceinline__ void run_z(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
-  if (!a.src) xf(buf, a.g.spt);
-  pw_combine_fast(a, buf, tile);
-  __syncthreads();
-  xf(buf, a.g.spt);
-  store_tile_fast(a.g, tile, buf, a.P, a.g.spt);
-}
-
-template <typename T, class XF>
-__device__ __forceinline__ void run_xadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf,
-                                         double* pacc) {
-  xf(buf, a.g.spt);
-  pw_adj_reaction(a, buf, tile, pacc);
-  __syncthreads();
-  xf(buf, a.g.spt);
-  store_tile_fast(a.g, tile, buf, a.P, a.g.spt);
-}
-
-template <typename T, class XF>
-__device__ __forceinline__ void run_zadj(const StageArgs<T>& a, T* buf, long long tile, XF& xf) {
-  xf(buf, a.g.spt);
-  pw_adj_combine(a, buf, tile);
-  __syncthreads();
-  xf(buf, a.g.spt);
-  store_tile_fast(a.g, tile, buf, a.P, a.g.spt);
 }
 
 // Dense transform as a functor (one tile per block).

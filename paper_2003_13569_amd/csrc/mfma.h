@@ -180,8 +180,8 @@ struct MfmaXfF32 {
   // fold work item of this thread: column col, entries i0 .. i0+7
   bool ffast;
   int i0, col, fa, fbb;
-  // output rows of this lane's results (direct unfold), per row block
-  int xrow[2], rmask[2];
+  // first output row of this lane's results (direct unfold), per row block
+  int rmask[2], orow[2];
 
   __device__ __forceinline__ MfmaXfF32(const Geom*, const MfmaAxisDev* ax_, float* fb_)
       : ax(ax_), fb(reinterpret_cast<unsigned short*>(fb_)) {
@@ -211,7 +211,7 @@ struct MfmaXfF32 {
       // direct unfold: E row m -> output 2m, O row m -> output 2m + 1
       const int mb = 16 * (isO[h] ? rb - ax->RBe : rb) + 4 * (lane / 16);
       const int row0 = 2 * mb + (isO[h] ? 1 : 0);
-      xrow[h] = row0 * P + lane % 16;
+      orow[h] = row0;
       rmask[h] = 0;
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -348,6 +348,28 @@ struct MfmaXfF32 {
     }
   }
 
+  // DCT-I / DST-I transform of one species' tile x with the results written
+  // straight to global memory: row k of the tile to g + k inner (16 lanes
+  // write 64 contiguous bytes). The tile in LDS is left as it was.
+  __device__ __forceinline__ void to_global(const float* x, float* g, long long inner) {
+    fold(x);
+    __syncthreads();
+    f32x4 acc[2][CB];
+    products(acc);
+    const int lane = threadIdx.x % 64;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float* gr = g + orow[h] * inner + lane % 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (rmask[h] & (1 << r)) {
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) gr[2 * r * inner + 16 * cb] = acc[h][cb][r];
+        }
+      }
+    }
+  }
+
   __device__ __forceinline__ void operator()(float* buf, int S) {
     const int lane = threadIdx.x % 64;
     for (int s = 0; s < S; ++s) {
@@ -359,7 +381,7 @@ struct MfmaXfF32 {
       if (direct) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          float* xr = x + xrow[h];
+          float* xr = x + orow[h] * P + lane % 16;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             if (rmask[h] & (1 << r)) {
@@ -1240,9 +1262,14 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
       combine_pre<MODE>(a, buf, tile, ld, lam_lds);
       ld.issue(a, next);
       __syncthreads();
-      xf(buf, 1);
-      tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
-      __syncthreads();
+      if (ax.direct) {
+        // inverse transform straight to the field
+        xf.to_global(buf, a.P + tile_ref(a.g, tile).base, a.g.inner);
+      } else {
+        xf(buf, 1);
+        tile_store<T, XF::W, FAST, false>(a.g, tile, buf, a.P);
+        __syncthreads();
+      }
       pipe.commit(a.g, next, src, buf);
       __syncthreads();
     }
@@ -1416,18 +1443,28 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
       pb.issue(g, nxt(blockIdx.x + G), a.src);
       pa.commit(g, blockIdx.x, a.src, buf);
       __syncthreads();
+      // results of DCT-I / DST-I transforms go straight to global memory
+      const bool direct = ax.direct != 0 && g.spt == 1;
       for (long long tile = blockIdx.x; tile < g.ntiles; tile += 2 * G) {
         pa.issue(g, nxt(tile + 2 * G), a.src);
-        xf(buf, g.spt);
-        tile_store<T, XF::W, FAST, XF::XAX>(g, tile, buf, a.dst);
-        __syncthreads();
+        if (direct) {
+          xf.to_global(buf, a.dst + tile_ref(g, tile).base, g.inner);
+        } else {
+          xf(buf, g.spt);
+          tile_store<T, XF::W, FAST, XF::XAX>(g, tile, buf, a.dst);
+          __syncthreads();
+        }
         pb.commit(g, nxt(tile + G), a.src, buf);
         __syncthreads();
         if (tile + G >= g.ntiles) break;
         pb.issue(g, nxt(tile + 3 * G), a.src);
-        xf(buf, g.spt);
-        tile_store<T, XF::W, FAST, XF::XAX>(g, tile + G, buf, a.dst);
-        __syncthreads();
+        if (direct) {
+          xf.to_global(buf, a.dst + tile_ref(g, tile + G).base, g.inner);
+        } else {
+          xf(buf, g.spt);
+          tile_store<T, XF::W, FAST, XF::XAX>(g, tile + G, buf, a.dst);
+          __syncthreads();
+        }
         pa.commit(g, nxt(tile + 2 * G), a.src, buf);
         __syncthreads();
       }
