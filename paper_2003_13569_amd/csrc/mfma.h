@@ -252,6 +252,26 @@ struct MfmaXfF32 {
         dv[e] = b >= 0 ? xa - xb : 0.f;
       }
     }
+    fold_store(sv, dv);
+  }
+
+  // Fold from registers: v[0], v[1] hold entries i0 .. i0+7 of this thread's
+  // line, v[2], v[3] entries n-8-i0 .. n-1-i0 (DCT-I / DST-I pairs i, n-1-i;
+  // items past the folded length are padding).
+  __device__ __forceinline__ void fold_regs(const float4 (&v)[4]) {
+    float sv[8], dv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float xa = vget<float>(v[e >> 2], e & 3);
+      const float xb = vget<float>(v[2 + ((7 - e) >> 2)], (7 - e) & 3);
+      sv[e] = ffast ? xa + xb : 0.f;
+      dv[e] = ffast ? xa - xb : 0.f;
+    }
+    fold_store(sv, dv);
+  }
+
+  // Column scale, binary16 split and store of one fold item.
+  __device__ __forceinline__ void fold_store(const float (&sv)[8], const float (&dv)[8]) {
     float m = 0.f;
 #pragma unroll
     for (int e = 0; e < 8; ++e) m = fmaxf(m, fmaxf(fabsf(sv[e]), fabsf(dv[e])));
@@ -371,11 +391,18 @@ struct MfmaXfF32 {
   }
 
   __device__ __forceinline__ void operator()(float* buf, int S) {
-    const int lane = threadIdx.x % 64;
     for (int s = 0; s < S; ++s) {
       float* x = buf + s * n * P;
       fold(x);
       __syncthreads();
+      mfma_write(x);
+    }
+  }
+
+  // Products of the folded data in fb and their unfold into the tile x.
+  __device__ __forceinline__ void mfma_write(float* x) {
+    const int lane = threadIdx.x % 64;
+    {
       f32x4 acc[2][CB];
       products(acc);
       if (direct) {
@@ -1186,6 +1213,29 @@ __device__ __forceinline__ void combine_tile(const StageArgs<T>& a, T* buf, long
   pw_combine_fast(a, buf, tile);
 }
 
+// Inputs of the fold of an x tile (two species, 32 lines, n in {64, 128,
+// 256}, DCT-I / DST-I), read straight into registers: thread t takes line
+// (t/16) mod 32, entries i0 .. i0+7 and n-8-i0 .. n-1-i0 with i0 = 8 (t%16)
+// (padding items, i0 >= n/2, read entry 0 again and are dropped).
+struct XFoldLoads {
+  float4 v[2][4];
+  __device__ __forceinline__ void issue(const Geom& g, long long tile, const float* src) {
+    const long long t = tile < g.ntiles ? tile : g.ntiles - 1;
+    const int n = g.n;
+    const int i0 = (threadIdx.x & 15) << 3;
+    const int ic = 2 * i0 < n ? i0 : 0;
+    const long long line = t * 32 + ((threadIdx.x >> 4) & 31);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const float* p = src + s * g.total + line * n;
+      v[s][0] = *reinterpret_cast<const float4*>(p + ic);
+      v[s][1] = *reinterpret_cast<const float4*>(p + ic + 4);
+      v[s][2] = *reinterpret_cast<const float4*>(p + n - 8 - ic);
+      v[s][3] = *reinterpret_cast<const float4*>(p + n - 4 - ic);
+    }
+  }
+};
+
 // ------------------------------------------------------------------ kernels
 // Persistent: block b handles tiles b, b + gridDim.x, ... The loads of the
 // next tile are issued before the current one is computed and written to LDS
@@ -1199,11 +1249,40 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const int S = a.g.spt;
   const long long last = a.g.ntiles - 1;
+  bool bad = false;
+  if constexpr (FAST && std::is_same<T, float>::value) {
+    if (ax.direct && S == 2) {
+      // inverse-x folded straight from registers: no LDS staging of the input
+      XFoldLoads rl;
+      rl.issue(a.g, blockIdx.x, a.P);
+      for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
+        const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+        xf.fold_regs(rl.v[0]);
+        __syncthreads();
+        xf.mfma_write(buf);
+        xf.fold_regs(rl.v[1]);
+        rl.issue(a.g, next, a.P);
+        __syncthreads();
+        xf.mfma_write(buf + a.g.n * XF::P);
+        if (a.st_phys) {
+          XTileIO<XF::W>::store(a.g, tile_ref(a.g, tile), buf,
+                                a.st_phys + (long long)a.mode * S * a.g.total);
+          __syncthreads();
+        }
+        bad |= pw_reaction(a, buf, tile, false);
+        __syncthreads();
+        xf(buf, S);
+        tile_store<T, XF::W, FAST, true>(a.g, tile, buf, a.P);
+        __syncthreads();
+      }
+      if (bad) a.flag[0] = 1;
+      return;
+    }
+  }
   TilePipe<T, XF::W, FAST, true> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
   pipe.commit(a.g, blockIdx.x, a.P, buf);
   __syncthreads();
-  bool bad = false;
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
     const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
     pipe.issue(a.g, next, a.P);
