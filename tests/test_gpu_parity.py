@@ -56,6 +56,8 @@ VEC_CASES = [
         (0.05, 1.0), 0.01, "schnak_noise", (0.0, 1.0)),
     _wl("gm2d-neu-vec", "neumann", (256, 128), "gierer_meinhardt", GM, (1.6, 1.4), (1e-3, 0.05),
         0.05, "gm_noise", (0.0, 2.0)),
+    _wl("gs3d-per-vec", "periodic", (64, 64, 64), "gray_scott", GS, (1.7, 1.9), (2e-3, 1e-3), 0.5,
+        "gs_square", (-1.0, 1.0)),
 ]
 VEC_IDS = [c.name for c in VEC_CASES]
 
