@@ -532,7 +532,7 @@ using XfZ = typename XfSel<T>::Z;
 // tiles use the generic paths of kernels.h.
 //
 // Strided axis (W = 32, one species per tile, n a multiple of 64 up to 256):
-// thread t moves rows t/8 + 64k, lanes 4(t%8) .. +3.
+// thread t moves rows row0(t) + 64k, lanes 4(t%8) .. +3.
 // x axis (W = 16 lines, every species, n in {64, 128, 256}, 128 <= S n <= 512): a wave moves
 // 16 consecutive vectors of each of 4 lines, so that the four scalar LDS
 // writes of a vector land in distinct banks across the wave.
@@ -546,7 +546,13 @@ struct TileIO {
 template <>
 struct TileIO<float, 32> {
   static constexpr int P = 33, VPR = 8, RSTEP = 512 / VPR, MAXK = 4;
-  __device__ __forceinline__ static int row0() { return threadIdx.x / VPR; }
+  // Wave w moves rows 4w .. 4w+3 and 4w+32 .. 4w+35 (8 lanes per row): with
+  // the pitch of 33 floats the four scalar LDS accesses of a vector then hit
+  // 64 distinct banks across the wave (rows r and r+4 would collide).
+  __device__ __forceinline__ static int row0() {
+    const int l = threadIdx.x & 63, rr = l >> 3;
+    return 4 * (int)(threadIdx.x >> 6) + (rr & 3) + 32 * (rr >> 2);
+  }
   __device__ __forceinline__ static int lane4() { return (threadIdx.x % VPR) * 4; }
   __device__ __forceinline__ static void issue(const Geom& g, const TileRef& tr, const float* src,
                                                float4* v) {
