@@ -75,18 +75,33 @@ enum sfrde_scheme { SFRDE_SCHEME_P13 = 0, SFRDE_SCHEME_EXP = 1 };
  *                     f_u = gamma(a - u + u^2 v),  f_v = gamma(b - u^2 v)
  *   GIERER_MEINHARDT  p = (rho, mu_u, sigma_u, sigma_v, mu_v)
  *                     f_u = rho - mu_u u + sigma_u u^2/v,  f_v = sigma_v u^2 - mu_v v
- * All but LINEAR need S = 2. */
+ * FHN .. GIERER_MEINHARDT need S = 2.
+ * Manufactured-solution problems of Section 5.1 (S = 1, no parameters: the
+ * source is built from the plan's kappa and alpha; x_j is the node position
+ * on [0, 1], x_j = j h for periodic and Neumann, (j + 1) h for Dirichlet):
+ *   HUXLEY_MMS   Example 2, 2D, periodic or Neumann:
+ *                f = u(1-u)(u-1) + s(x, y, t), with s making
+ *                u = t^alpha cos^3(2 pi x) cos^3(2 pi y) the exact solution
+ *   FISHER_MMS   Example 1, 1D, Dirichlet:
+ *                f = u - u^2 + s(x, t), with s making
+ *                u = e^-t sin^3(2 pi x) the exact solution
+ * The sources are evaluated in FP64 at each stage's time. sfrde_backward
+ * returns u0 gradients for them; kappa, alpha and parameter gradients are
+ * SFRDE_EUNSUPPORTED (the sources depend on kappa and alpha). */
 enum sfrde_reaction {
   SFRDE_RXN_LINEAR = 0,
   SFRDE_RXN_FHN = 1,
   SFRDE_RXN_GRAY_SCOTT = 2,
   SFRDE_RXN_SCHNAKENBERG = 3,
-  SFRDE_RXN_GIERER_MEINHARDT = 4
+  SFRDE_RXN_GIERER_MEINHARDT = 4,
+  SFRDE_RXN_HUXLEY_MMS = 5,
+  SFRDE_RXN_FISHER_MMS = 6
 };
 
 /* Create a plan (Sections 3-4; Alg. 1 precompute).
  *   out       receives the plan handle (host pointer, required)
- *   ndim      2 or 3 (1 returns SFRDE_EUNSUPPORTED)
+ *   ndim      1, 2 or 3 (a 1D plan runs as a 2D one whose second axis has
+ *             one point, eigenvalue 0 and the identity transform)
  *   n[ndim]   unknowns per axis, x first; each >= 2, each <= 1024
  *   bc        enum sfrde_bc, the same on every axis
  *   h[ndim]   mesh width per axis (> 0)

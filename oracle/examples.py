@@ -35,6 +35,13 @@ from .separable import SeparableScheme
 
 def example1(N: int, alpha: float, kappa: float, tau: float, T: float):
     """Solve Example 1 with N intervals; returns (max error at T, steps)."""
+    U, exact, M = example1_fields(N, alpha, kappa, tau, T)
+    return float(np.max(np.abs(U - exact))), M
+
+
+def example1_fields(N: int, alpha: float, kappa: float, tau: float, T: float):
+    """Example 1 with N intervals: (computed u at T, exact u at T, steps), on
+    the N - 1 interior nodes."""
     h = 1.0 / N
     x = np.arange(1, N) * h
     s1 = np.sin(2 * np.pi * x)
@@ -51,12 +58,20 @@ def example1(N: int, alpha: float, kappa: float, tau: float, T: float):
     sch = SeparableScheme("dirichlet", (N - 1,), (h,), (alpha,), (kappa,), tau)
     U = sch.integrate((s1 ** 3)[None], M, Nfun)
     exact = np.exp(-M * tau) * s1 ** 3
-    return float(np.max(np.abs(U[0] - exact))), M
+    return U[0], exact, M
 
 
 def example2(bc: str, inv_h: int, alpha: float, kappa: float = 1.0, T: float = 1.0,
              tau_over_h: float = 0.1):
     """Solve Example 2; returns (max error at T, steps)."""
+    U, exact, M = example2_fields(bc, inv_h, alpha, kappa, T, tau_over_h)
+    return float(np.max(np.abs(U - exact))), M
+
+
+def example2_fields(bc: str, inv_h: int, alpha: float, kappa: float = 1.0, T: float = 1.0,
+                    tau_over_h: float = 0.1):
+    """Example 2: (computed u at T, exact u at T, steps), indexed [y, x] over
+    the nodes x_j = j h."""
     h = 1.0 / inv_h
     n = inv_h if bc == "periodic" else inv_h + 1
     x = np.arange(n) * h
@@ -80,4 +95,4 @@ def example2(bc: str, inv_h: int, alpha: float, kappa: float = 1.0, T: float = 1
     sch = SeparableScheme(bc, (n, n), (h, h), (alpha,), (kappa,), tau)
     U = sch.integrate(np.zeros((1, n, n)), M, Nfun)
     exact = (M * tau) ** alpha * CC
-    return float(np.max(np.abs(U[0] - exact))), M
+    return U[0], exact, M

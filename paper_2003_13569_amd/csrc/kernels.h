@@ -309,7 +309,7 @@ __device__ __forceinline__ double point_weight(long long idx, long long n0, long
   long long i2 = (r / n1) % n2;  // species-split tiles index past the first species
   double w = 1.0;
   if (i0 == 0 || i0 == n0 - 1) w *= 0.5;
-  if (i1 == 0 || i1 == n1 - 1) w *= 0.5;
+  if (n1 > 1 && (i1 == 0 || i1 == n1 - 1)) w *= 0.5;  // n1 = 1: the padding axis of 1D
   if (n2 > 1 && (i2 == 0 || i2 == n2 - 1)) w *= 0.5;
   return w;
 }
@@ -363,6 +363,38 @@ struct StageArgs {
 // Each phase walks the tile's elements in the coalescing order and works on
 // the LDS buffer buf[s][j][w] in place.
 
+// Manufactured sources of Examples 1 and 2 (Section 5.1) at node idx and time
+// t, in FP64: s = u_t + kappa (-Delta)^(alpha/2) u - f(u) at the exact u, with
+// the fractional Laplacian of the products of cosines (sines) taken from their
+// eigenvalues on the continuous domain. Constants c = p[MMS_P0..]:
+//   Example 2: (alpha, K1, K2, K3, hx, hy) with K1 = 9 kappa (8 pi^2)^(alpha/2)/16,
+//              K2 = 3 kappa (40 pi^2)^(alpha/2)/16, K3 = kappa (72 pi^2)^(alpha/2)/16
+//   Example 1: (alpha, K1, -, K3, h) with K1 = 3 kappa (2 pi)^alpha/4,
+//              K3 = kappa (6 pi)^alpha/4
+__device__ __forceinline__ double mms_source(const Rxn& r, double t, long long idx,
+                                             long long n0, long long n1) {
+  const double* c = r.p + MMS_P0;
+  const long long i0 = idx % n0;
+  if (r.kind == RXN_FISHER_MMS) {
+    // u = e^-t sin^3(2 pi x), sin^3 = (3 sin(2 pi x) - sin(6 pi x))/4, interior nodes
+    const double x = double(i0 + 1) * c[4];
+    const double s1 = sinpi(2.0 * x), s3 = sinpi(6.0 * x);
+    const double e = exp(-t), s13 = s1 * s1 * s1;
+    return -2.0 * e * s13 + e * (c[1] * s1 - c[3] * s3) + e * e * s13 * s13;
+  }
+  // u = t^alpha C(x) C(y), C = cos^3(2 pi .) = (3 cos(2 pi .) + cos(6 pi .))/4
+  const long long i1 = (idx / n0) % n1;
+  const double x = double(i0) * c[4], y = double(i1) * c[5];
+  const double c1x = cospi(2.0 * x), c3x = cospi(6.0 * x);
+  const double c1y = cospi(2.0 * y), c3y = cospi(6.0 * y);
+  const double cc = c1x * c1x * c1x * c1y * c1y * c1y;
+  const double phi = c[1] * c1x * c1y + c[2] * (c3x * c1y + c1x * c3y) + c[3] * c3x * c3y;
+  const double ta = t > 0.0 ? pow(t, c[0]) : 0.0;
+  const double dta = t > 0.0 ? c[0] * ta / t : 0.0;
+  const double w = ta * cc;
+  return dta * cc + ta * phi - w * (1.0 - w) * (w - 1.0);
+}
+
 // Forward reaction: buf holds the stage value (physical); replaced by f.
 // Walks the LDS tile row by row (lanes w fastest); the global index is only
 // formed when stage values are stored.
@@ -388,6 +420,12 @@ __device__ __forceinline__ bool pw_reaction_n(const StageArgs<T>& a, T* buf, lon
       for (int s = 0; s < NS; ++s) a.st_phys[((long long)a.mode * NS + s) * g.total + idx] = u[s];
     }
     rxn_eval_t<T, NS>(rx, u, f);
+    if constexpr (NS == 1) {
+      if (rx.kind >= RXN_HUXLEY_MMS) {
+        const long long idx = tr.base + (long long)j * tr.rs + (long long)w * tr.cs;
+        f[0] += T(mms_source(a.rxn, a.t, idx, a.n0, a.n1));
+      }
+    }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       bad |= !isfinite(u[s]) || !isfinite(f[s]);

@@ -6,10 +6,21 @@
 
 namespace sfrde {
 
-enum { RXN_LINEAR = 0, RXN_FHN = 1, RXN_GRAY_SCOTT = 2, RXN_SCHNAKENBERG = 3, RXN_GM = 4 };
+enum {
+  RXN_LINEAR = 0,
+  RXN_FHN = 1,
+  RXN_GRAY_SCOTT = 2,
+  RXN_SCHNAKENBERG = 3,
+  RXN_GM = 4,
+  RXN_HUXLEY_MMS = 5,  // Example 2 of Section 5.1 (one species, 2D, with a source)
+  RXN_FISHER_MMS = 6   // Example 1 of Section 5.1 (one species, 1D, with a source)
+};
 constexpr int MAX_SPECIES = 4;
 constexpr int MAX_PARAMS = 16;
 constexpr int RXN_NP_MAX = 5;  // parameters of any of the models (linear: one per species)
+// Manufactured-source constants sit in p[MMS_P0..]: alpha, three source
+// weights, the mesh widths (x, y); filled by the host, never user parameters.
+constexpr int MMS_P0 = 8;
 
 struct Rxn {
   int kind;
@@ -40,6 +51,12 @@ __device__ __forceinline__ void rxn_eval_t(const RxnT<T>& r, const T* u, T* f) {
       for (int s = 0; s < NS; ++s) f[s] = r.lin[s] * u[s];
       break;
     default:
+      if constexpr (NS == 1) {
+        // the pointwise parts of Examples 1 and 2 (the source is added by
+        // the caller, which knows the point and the stage time)
+        const T x = u[0];
+        f[0] = r.kind == RXN_HUXLEY_MMS ? x * (T(1) - x) * (x - T(1)) : x - x * x;
+      }
       if constexpr (NS == 2) {
         const T x = u[0], v = u[1];
         switch (r.kind) {
@@ -69,46 +86,6 @@ __device__ __forceinline__ void rxn_eval_t(const RxnT<T>& r, const T* u, T* f) {
   }
 }
 
-// f = f(u); u and f hold S values.
-template <typename T>
-__device__ __forceinline__ void rxn_eval(const Rxn& r, const T* u, T* f) {
-  switch (r.kind) {
-    case RXN_LINEAR:
-      for (int s = 0; s < r.S; ++s) f[s] = T(r.p[s]) * u[s];
-      break;
-    case RXN_FHN: {
-      const T mu = T(r.p[0]), eps = T(r.p[1]), beta = T(r.p[2]), gam = T(r.p[3]), dlt = T(r.p[4]);
-      const T x = u[0], v = u[1];
-      f[0] = x * (T(1) - x) * (x - mu) - v;
-      f[1] = eps * (beta * x - gam * v - dlt);
-      break;
-    }
-    case RXN_GRAY_SCOTT: {
-      const T F = T(r.p[0]), K = T(r.p[1]);
-      const T x = u[0], v = u[1];
-      const T xvv = x * v * v;
-      f[0] = -xvv + F * (T(1) - x);
-      f[1] = xvv - (F + K) * v;
-      break;
-    }
-    case RXN_SCHNAKENBERG: {
-      const T g = T(r.p[0]), a = T(r.p[1]), b = T(r.p[2]);
-      const T x = u[0], v = u[1];
-      const T xxv = x * x * v;
-      f[0] = g * (a - x + xxv);
-      f[1] = g * (b - xxv);
-      break;
-    }
-    default: {  // Gierer-Meinhardt
-      const T rho = T(r.p[0]), mu_u = T(r.p[1]), s_u = T(r.p[2]), s_v = T(r.p[3]), mu_v = T(r.p[4]);
-      const T x = u[0], v = u[1];
-      f[0] = rho - mu_u * x + s_u * x * x / v;
-      f[1] = s_v * x * x - mu_v * v;
-      break;
-    }
-  }
-}
-
 // out = J_f(u)^T g (out_r = sum_s g_s d f_s / d u_r), and
 // pacc[k] += wgt * sum_s g_s d f_s / d p_k.
 template <typename T, int NS>
@@ -121,6 +98,12 @@ __device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g
       if (want_p) pacc[s] += wgt * double(g[s] * u[s]);
     }
     return;
+  }
+  if constexpr (NS == 1) {
+    // Examples 1 and 2: the sources do not depend on u
+    const T x = u[0];
+    out[0] = r.kind == RXN_HUXLEY_MMS ? -g[0] * (x - T(1)) * (T(3) * x - T(1))
+                                      : g[0] * (T(1) - T(2) * x);
   }
   if constexpr (NS == 2) {
   switch (r.kind) {

@@ -178,6 +178,8 @@ int expected_nparams(int reaction, int S) {
     case RXN_GRAY_SCOTT: return 2;
     case RXN_SCHNAKENBERG: return 3;
     case RXN_GM: return 5;
+    case RXN_HUXLEY_MMS:
+    case RXN_FISHER_MMS: return 0;
     default: return -1;
   }
 }
@@ -186,6 +188,10 @@ int expected_nparams(int reaction, int S) {
 std::vector<double> axis_matrix_t(int bc, long long n) {
   const double pi = 3.14159265358979323846;
   std::vector<double> Mt((size_t)n * n);
+  if (n == 1) {  // the one-point padding axis of a 1D plan: the identity
+    Mt[0] = 1.0;
+    return Mt;
+  }
   for (long long k = 0; k < n; ++k) {
     for (long long j = 0; j < n; ++j) {
       double v;
@@ -211,6 +217,7 @@ std::vector<double> axis_matrix_t(int bc, long long n) {
 }
 
 double axis_inverse_scale(int bc, long long n) {
+  if (n == 1) return 1.0;  // padding axis of a 1D plan
   if (bc == SFRDE_BC_PERIODIC) return 1.0 / double(n);
   if (bc == SFRDE_BC_DIRICHLET) return 2.0 / double(n + 1);
   return 2.0 / double(n - 1);
@@ -363,6 +370,7 @@ double half_entry(const MfmaTables& t, int rb, int row16, int k) {
 int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   const char* env = getenv("SFRDE_TRANSFORM");
   if (env && strcmp(env, "dense") == 0) return SFRDE_OK;
+  if (p->n[axis] < 2) return SFRDE_OK;  // padding axis of a 1D plan: dense kernels
   MfmaTables t = mfma_tables(p->bc, p->n[axis]);
   if (!t.ok) return SFRDE_OK;
   const bool f32 = p->dtype == SFRDE_F32;
@@ -1068,9 +1076,17 @@ int validate(int32_t ndim, const int64_t* n, int32_t bc, const double* h, int32_
       return fail(SFRDE_EINVAL, "kappa[%d] must be finite and >= 0", s);
   }
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SFRDE_EINVAL, "dt must be finite and > 0");
-  if (reaction < 0 || reaction > 4) return fail(SFRDE_EINVAL, "unknown reaction %d", reaction);
-  if (reaction != RXN_LINEAR && S != 2)
+  if (reaction < 0 || reaction > RXN_FISHER_MMS)
+    return fail(SFRDE_EINVAL, "unknown reaction %d", reaction);
+  if (reaction >= RXN_HUXLEY_MMS) {
+    if (S != 1) return fail(SFRDE_EINVAL, "reaction %d needs exactly 1 species", reaction);
+    if (reaction == RXN_HUXLEY_MMS && (ndim != 2 || bc == SFRDE_BC_DIRICHLET))
+      return fail(SFRDE_EINVAL, "the Example 2 source is for 2D periodic or Neumann grids");
+    if (reaction == RXN_FISHER_MMS && (ndim != 1 || bc != SFRDE_BC_DIRICHLET))
+      return fail(SFRDE_EINVAL, "the Example 1 source is for 1D Dirichlet grids");
+  } else if (reaction != RXN_LINEAR && S != 2) {
     return fail(SFRDE_EINVAL, "reaction %d needs exactly 2 species", reaction);
+  }
   if (nparams != expected_nparams(reaction, S))
     return fail(SFRDE_EINVAL, "reaction %d takes %d parameters (got %d)", reaction,
                 expected_nparams(reaction, S), nparams);
@@ -1080,7 +1096,6 @@ int validate(int32_t ndim, const int64_t* n, int32_t bc, const double* h, int32_
   if (dtype != SFRDE_F32 && dtype != SFRDE_F64) return fail(SFRDE_EINVAL, "unknown dtype %d", dtype);
   if (scheme != SFRDE_SCHEME_P13 && scheme != SFRDE_SCHEME_EXP)
     return fail(SFRDE_EINVAL, "unknown scheme %d", scheme);
-  if (ndim == 1) return fail(SFRDE_EUNSUPPORTED, "1D grids are not supported by this build");
   return SFRDE_OK;
 }
 
@@ -1105,7 +1120,8 @@ int build_plan(sfrde_plan_s* p) {
     else
       TRY(upload_matrix<double>(p, a));
     std::vector<double> lam(p->n[a]);
-    for (long long k = 0; k < p->n[a]; ++k) lam[k] = axis_eigenvalue(p->bc, p->n[a], p->h[a], k);
+    for (long long k = 0; k < p->n[a]; ++k)
+      lam[k] = p->n[a] == 1 ? 0.0 : axis_eigenvalue(p->bc, p->n[a], p->h[a], k);
     TRY(dev_alloc(p, (void**)&p->lam[a], lam.size() * sizeof(double)));
     HIPCHECK(hipMemcpy(p->lam[a], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
   }
@@ -1206,13 +1222,19 @@ int sfrde_plan(sfrde_plan_t* out, int32_t ndim, const int64_t* n, int32_t bc, co
                scheme));
   sfrde_plan_s* p = new (std::nothrow) sfrde_plan_s();
   if (!p) return fail(SFRDE_ENOMEM, "host allocation of the plan failed");
-  p->ndim = ndim;
-  p->total = 1;
+  // A 1D plan runs as a 2D one whose second axis has one point (eigenvalue
+  // 0, identity transform, weight 1): the field layout is the same.
+  p->ndim = ndim == 1 ? 2 : ndim;
+  p->n[1] = 1;
+  p->h[1] = 1.0;
   for (int a = 0; a < ndim; ++a) {
     p->n[a] = n[a];
     p->h[a] = h[a];
-    p->total *= n[a];
-    p->cs *= axis_inverse_scale(bc, n[a]);
+  }
+  p->total = 1;
+  for (int a = 0; a < p->ndim; ++a) {
+    p->total *= p->n[a];
+    p->cs *= axis_inverse_scale(bc, p->n[a]);
   }
   p->bc = bc;
   p->S = nspecies;
@@ -1225,11 +1247,28 @@ int sfrde_plan(sfrde_plan_t* out, int32_t ndim, const int64_t* n, int32_t bc, co
   p->rxn.S = nspecies;
   p->rxn.np = nparams;
   for (int k = 0; k < nparams; ++k) p->rxn.p[k] = params[k];
+  if (reaction >= RXN_HUXLEY_MMS) {
+    // source constants of Examples 1 and 2 (Section 5.1), see mms_source()
+    const double pi = 3.14159265358979323846, a = alpha[0], k = kappa[0];
+    double* c = p->rxn.p + MMS_P0;
+    c[0] = a;
+    if (reaction == RXN_HUXLEY_MMS) {
+      c[1] = k / 16.0 * 9.0 * pow(8.0 * pi * pi, 0.5 * a);
+      c[2] = k / 16.0 * 3.0 * pow(40.0 * pi * pi, 0.5 * a);
+      c[3] = k / 16.0 * pow(72.0 * pi * pi, 0.5 * a);
+    } else {
+      c[1] = k / 4.0 * 3.0 * pow(2.0 * pi, a);
+      c[2] = 0.0;
+      c[3] = k / 4.0 * pow(6.0 * pi, a);
+    }
+    c[4] = h[0];
+    c[5] = ndim > 1 ? h[1] : 0.0;
+  }
   p->dtype = dtype;
   p->scheme = scheme;
   p->stream = (hipStream_t)hip_stream;
   p->w = dtype == SFRDE_F32 ? 4 : 8;
-  for (int a = 0; a < ndim; ++a) make_geom(p, a);
+  for (int a = 0; a < p->ndim; ++a) make_geom(p, a);
   int rc = build_plan(p);
   if (rc != SFRDE_OK) {
     std::string msg = g_err;
@@ -1301,6 +1340,9 @@ int sfrde_backward(sfrde_plan_t p, const void* ckpt, int64_t nsteps, int64_t ckp
   if (!ckpt || !grad_uT) return fail(SFRDE_EINVAL, "ckpt and grad_uT must not be NULL");
   if (nsteps < 1 || ckpt_every < 1) return fail(SFRDE_EINVAL, "nsteps, ckpt_every must be >= 1");
   TRY(check_header(p, ckpt, nsteps, ckpt_every));
+  if (p->rxn.kind >= RXN_HUXLEY_MMS && (grad_kappa || grad_alpha))
+    return fail(SFRDE_EUNSUPPORTED,
+                "kappa and alpha gradients of the manufactured sources are not implemented");
   if (p->dtype == SFRDE_F32)
     return backward_t<float>(p, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0, grad_kappa,
                              grad_alpha, grad_params);

@@ -14,7 +14,8 @@ OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -
 BC = {"periodic": 0, "dirichlet": 1, "neumann": 2}
 DTYPE = {"f32": 0, "f64": 1}
 SCHEME = {"p13": 0, "exp": 1}
-REACTION = {"linear": 0, "fhn": 1, "gray_scott": 2, "schnakenberg": 3, "gierer_meinhardt": 4}
+REACTION = {"linear": 0, "fhn": 1, "gray_scott": 2, "schnakenberg": 3, "gierer_meinhardt": 4,
+            "huxley_mms": 5, "fisher_mms": 6}
 CKPT_HEADER_BYTES = 256
 MAX_PARAMS = 16
 

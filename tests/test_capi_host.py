@@ -53,11 +53,30 @@ def test_plan_rejects_bad_arguments_without_a_device(field, value):
     assert C.sfrde_last_error()
 
 
-def test_one_dimensional_grids_are_reported_unsupported():
-    kw = dict(GOOD, ndim=1, n=[8], h=[0.1])
+HUX = dict(GOOD, nspecies=1, alpha=[1.5], kappa=[1.0], reaction=C.REACTION["huxley_mms"],
+           nparams=0, params=[], bc=0)
+FIS = dict(GOOD, ndim=1, n=[15], h=[1 / 16], bc=1, nspecies=1, alpha=[1.8], kappa=[10.0],
+           reaction=C.REACTION["fisher_mms"], nparams=0, params=[])
+BAD_MMS = [
+    ("huxley-2species", dict(HUX, nspecies=2, alpha=[1.5, 1.5], kappa=[1.0, 1.0])),
+    ("huxley-3d", dict(HUX, ndim=3, n=[8, 6, 4], h=[0.1] * 3)),
+    ("huxley-1d", dict(HUX, ndim=1, n=[8], h=[0.1])),
+    ("huxley-dirichlet", dict(HUX, bc=1)),
+    ("huxley-param", dict(HUX, nparams=1, params=[1.0])),
+    ("fisher-2d", dict(FIS, ndim=2, n=[15, 15], h=[1 / 16] * 2)),
+    ("fisher-periodic", dict(FIS, bc=0)),
+    ("fisher-neumann", dict(FIS, bc=2)),
+    ("1d-one-point", dict(FIS, n=[1])),
+]
+
+
+@pytest.mark.parametrize("kw", [k for _, k in BAD_MMS], ids=[i for i, _ in BAD_MMS])
+def test_manufactured_sources_reject_other_problems(kw):
+    """Examples 1 and 2 of Section 5.1 define their sources for one species on
+    the 1D Dirichlet and 2D periodic/Neumann unit domains only."""
     with pytest.raises(C.SfrdeError) as ei:
         C.sfrde_plan(**kw)
-    assert ei.value.code == C.EUNSUPPORTED
+    assert ei.value.code == C.EINVAL
 
 
 def test_reaction_needs_two_species():
