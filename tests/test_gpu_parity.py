@@ -108,6 +108,16 @@ def test_dense_axes_match_oracle(wl, dtype, tol):
     assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
 
 
+# The paper's own applications (Section 5.2) at its grids, constants and
+# deterministic initial data; GM with different orders per species.
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+@pytest.mark.parametrize("wl", W.PAPER, ids=[c.name for c in W.PAPER])
+def test_paper_applications_match_oracle(wl, dtype, tol):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 5)
+    assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
+
+
 def test_linear_reaction_many_species():
     wl = W.Workload(name="lin4", bc="dirichlet", shape=(14, 19), domain=(0.0, 1.0),
                     alpha=(1.2, 1.5, 1.8, 2.0), kappa=(0.01, 0.02, 0.0, 0.05),

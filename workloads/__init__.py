@@ -126,6 +126,39 @@ def initial_fields(wl: Workload) -> np.ndarray:
         if wl.ndim == 2:
             u, v = _box5(u), _box5(v)
         return np.stack([u, v])
+    # Deterministic initial data of the paper's applications (Section 5.2);
+    # no random draws.
+    if wl.init == "paper_fhn":
+        # u = 1 on 0 < x <= 0.125, 0 < y < 0.125; v = 0.1 on 0.125 <= y < 2.5
+        y, x = np.meshgrid(wl.coords(0), wl.coords(1), indexing="ij")
+        u = np.where((x > 0) & (x <= 0.125) & (y > 0) & (y < 0.125), 1.0, 0.0)
+        v = np.where((y >= 0.125) & (y < 2.5), 0.1, 0.0)
+        return np.stack([u, v])
+    if wl.init == "paper_gm":
+        # u = (1 + 0.001 sum_{j=1..20} cos(pi j y / 2)) sech^2(r / (2 eps)) / 2,
+        # v = cosh(1 - r) / (3 cosh 1), r = |(x, y)|
+        eps = float(wl.extra["eps"])
+        y, x = np.meshgrid(wl.coords(0), wl.coords(1), indexing="ij")
+        r = np.sqrt(x * x + y * y)
+        ripple = sum(np.cos(0.5 * np.pi * j * y) for j in range(1, 21))
+        u = 0.5 * (1.0 + 0.001 * ripple) / np.cosh(r / (2.0 * eps)) ** 2
+        v = np.cosh(1.0 - r) / (3.0 * np.cosh(1.0))
+        return np.stack([u, v])
+    if wl.init == "paper_gs":
+        # (u, v) = (1/2, 1/4) in the disk (x-1/2)^2 + (y-1/2)^2 <= 0.0016, else (1, 0)
+        y, x = np.meshgrid(wl.coords(0), wl.coords(1), indexing="ij")
+        inside = (x - 0.5) ** 2 + (y - 0.5) ** 2 <= 0.0016
+        return np.stack([np.where(inside, 0.5, 1.0), np.where(inside, 0.25, 0.0)])
+    if wl.init == "paper_schnak":
+        # u = 1 - exp(-10 (X^2 + Y^2 + Z^2)), v = exp(-10 (X^2 + 2 Y^2 + Z^2)),
+        # X = x - l/2 etc. on (0, l)^3
+        lo, hi = wl.domain
+        c = 0.5 * (lo + hi)
+        z, y, x = np.meshgrid(wl.coords(0) - c, wl.coords(1) - c, wl.coords(2) - c,
+                              indexing="ij")
+        u = 1.0 - np.exp(-10.0 * (x * x + y * y + z * z))
+        v = np.exp(-10.0 * (x * x + 2.0 * y * y + z * z))
+        return np.stack([u, v])
     if wl.init == "normal":
         base = np.asarray(wl.extra.get("mean", [0.5] * wl.nspecies))
         sd = float(wl.extra.get("sd", 0.1))
@@ -172,6 +205,42 @@ C5_SCHNAK_NEU = Workload(
            "target": {"alpha_shift": 0.05, "kappa_v_scale": 1.1}})
 
 ALL = (C1_FHN, C2_GS, C3_SCHNAK_DIR, C4_GM_ADJ, C5_SCHNAK_NEU)
+
+# The parameter sets, grids, steps and initial data of the paper's own
+# applications (Section 5.2). N is the paper's number of intervals; the
+# unknowns per axis follow the boundary condition (periodic: n = N). Where the
+# paper lists several orders or constants, the first listed is the preset and
+# the rest are in extra["sweep"].
+PAPER_FHN = Workload(
+    name="paper_fhn2d_periodic_256", bc="periodic", shape=(256, 256), domain=(0.0, 2.5),
+    alpha=(2.0, 2.0), kappa=(1e-4, 0.0), reaction="fhn", params=(0.1, 0.01, 0.5, 1.0, 0.0),
+    dt=1.0, nsteps=2000, seed=0, init="paper_fhn", dtype="f64",
+    extra={"sweep": {"alpha": (2.0, 1.7, 1.5), "bc": ("periodic", "neumann")}})
+
+# f_u = u^2/v - u, f_v = u^2/(eps mu) - v/mu as the Gierer-Meinhardt family with
+# (rho, mu_u, sigma_u, sigma_v, mu_v) = (0, 1, 1, 1/(eps mu), 1/mu);
+# kappa_u = eps^2, kappa_v = K/mu; orders (alpha, beta) per species.
+_GM_EPS, _GM_MU, _GM_K = 0.04, 0.1, 0.0162
+PAPER_GM = Workload(
+    name="paper_gm2d_neumann_64", bc="neumann", shape=(65, 65), domain=(-1.0, 1.0),
+    alpha=(2.0, 1.9), kappa=(_GM_EPS ** 2, _GM_K / _GM_MU), reaction="gierer_meinhardt",
+    params=(0.0, 1.0, 1.0, 1.0 / (_GM_EPS * _GM_MU), 1.0 / _GM_MU), dt=0.1, nsteps=10000,
+    seed=0, init="paper_gm", dtype="f64",
+    extra={"eps": _GM_EPS, "sweep": {"beta": (2.0, 1.9, 1.8), "K": (0.0162, 0.0128)}})
+
+PAPER_GS = Workload(
+    name="paper_gs2d_periodic_265", bc="periodic", shape=(265, 265), domain=(0.0, 1.0),
+    alpha=(2.0, 2.0), kappa=(2e-5, 1e-5), reaction="gray_scott", params=(0.03, 0.055),
+    dt=1.0, nsteps=8000, seed=0, init="paper_gs", dtype="f64",
+    extra={"sweep": {"alpha": (2.0, 1.7, 1.5), "K": (0.055, 0.061, 0.063)}})
+
+PAPER_SCHNAK = Workload(
+    name="paper_schnakenberg3d_periodic_32", bc="periodic", shape=(32, 32, 32),
+    domain=(0.0, 10.0), alpha=(2.0, 2.0), kappa=(1.0, 10.0), reaction="schnakenberg",
+    params=(1.0, 0.1, 0.9), dt=1.0, nsteps=200, seed=0, init="paper_schnak", dtype="f64",
+    extra={"sweep": {"alpha": (2.0, 1.5), "l": (10.0, 20.0, 40.0)}})
+
+PAPER = (PAPER_FHN, PAPER_GM, PAPER_GS, PAPER_SCHNAK)
 
 
 def small(wl: Workload, shape: tuple, nsteps: int | None = None, **kw) -> Workload:
