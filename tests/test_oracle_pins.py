@@ -358,3 +358,53 @@ def test_table1_example1_printed_errors():
         errs.append(err)
     orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(orders > 3.9)
+
+
+# ------------------------------------------------------------------ stability (Section 4.2.2)
+from oracle import stability
+
+
+@pytest.mark.parametrize("y", [0.0, -0.5, -3.0, -20.0, -250.0])
+def test_stability_amplification_matches_printed_quartic(y):
+    # The stages run on the test equation give eq. Eq41's quartic (with the
+    # y^2 term of c1's numerator that the printed formula lacks).
+    xs = np.array([0.3, -2.0 + 1.5j, 4.0 - 7.0j, -11.0 + 0.1j])
+    got = stability.amplification("p13", xs, y)
+    ref = _paper_r(xs, y)
+    assert np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-12
+    c = stability.amplification_poly("p13", y)
+    assert np.max(np.abs(np.polyval(c[::-1], xs) - ref) / np.maximum(1.0, np.abs(ref))) <= 1e-12
+
+
+@pytest.mark.parametrize("scheme", ["p13", "exp"])
+def test_stability_reduces_to_rk4_at_y0(scheme):
+    # Remark of Section 4.2.2: at y = 0 the factor is RK4's Taylor polynomial.
+    c = stability.amplification_poly(scheme, 0.0)
+    assert np.allclose(c, [1, 1, 1 / 2, 1 / 6, 1 / 24], rtol=0, atol=1e-14)
+    # RK4's real stability limit: |r(x, 0)| = 1 at x = -2.785293563...
+    roots = stability.boundary(scheme, 0.0, 2)[1]      # r = -1 has no real root;
+    roots0 = stability.boundary(scheme, 0.0, 1)[0]     # r = +1: x = 0 and x = -2.7853
+    real = np.sort(roots0[np.abs(roots0.imag) < 1e-9].real)
+    assert np.allclose(real, [-2.785293563405282, 0.0], atol=1e-9)
+    assert np.all(np.abs(roots.imag) > 1e-3)
+
+
+def test_stability_exp_scheme_zero_reaction_is_the_exponential():
+    for y in (-0.1, -2.0, -9.0):
+        assert abs(stability.amplification("exp", 0.0, y) - np.exp(y)) <= 1e-14
+        assert abs(stability.amplification("p13", 0.0, y)
+                   - (24 + 6 * y) / (24 - 18 * y + 6 * y * y - y ** 3)) <= 1e-14
+
+
+@pytest.mark.parametrize("scheme", ["p13", "exp"])
+@pytest.mark.parametrize("y", [-1.0, -10.0, -60.0])
+def test_stability_boundary_points_have_unit_modulus(scheme, y):
+    b = stability.boundary(scheme, y, 16)
+    r = stability.amplification(scheme, b.ravel(), y)
+    assert np.max(np.abs(np.abs(r) - 1.0)) <= 1e-9
+    # the regions grow as y decreases (Section 4.2.2): compare the leftmost
+    # real crossing with that of a less negative y
+    def left(yy):
+        rts = stability.boundary(scheme, yy, 2).ravel()
+        return np.min(rts[np.abs(rts.imag) < 1e-7].real)
+    assert left(y) < left(y / 2)
