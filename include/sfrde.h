@@ -199,6 +199,34 @@ int sfrde_axis_eigenvalues(int32_t bc, int64_t n, double h, double* out);
 int sfrde_eval_coefficients(int32_t scheme, double L, double dt, int32_t deriv,
                             double* out6);
 
+/* Linear stability (Section 4.2.2, eq. Eq41). The test equation
+ * u' + c u = gamma u, with y = -c tau (real, <= 0) and x = gamma tau
+ * (complex), is advanced one step by the scheme's four stages, with its
+ * coefficients at L = -y; the ratio u^{k+1}/u^k is the amplification factor
+ * r(x, y), a quartic in x. Both calls run one GPU thread per point in FP64,
+ * are enqueued on hip_stream (NULL: the default stream) and return without
+ * waiting for it. Points with y > 0 or non-finite inputs give NaN.
+ * Errors: EINVAL for an unknown scheme, sizes out of range, or NULL arrays
+ * with a non-zero size; EDEVICE if the launch fails.
+ *
+ * sfrde_amplification: r(x_i, y_i) for i < count.
+ *   x  device double[count][2] (real, imaginary)
+ *   y  device double[count]
+ *   r  device double[count][2], written
+ *
+ * sfrde_stability_boundary: points of the |r| = 1 contours. For each y_i
+ * (i < ny) and theta_k = 2 pi k / ntheta (k < ntheta), the four complex x
+ * with r(x, y_i) = e^{i theta_k} (Durand-Kerner iteration on the quartic).
+ *   y      device double[ny]
+ *   roots  device double[ny][ntheta][4][2], written; the four roots of one
+ *          (i, k) come in no particular order
+ *   poly   device double[ny][5], written with c_0..c_4 of
+ *          r(x, y_i) = sum_k c_k x^k; may be NULL */
+int sfrde_amplification(int32_t scheme, int64_t count, const double* x, const double* y,
+                        double* r, void* hip_stream);
+int sfrde_stability_boundary(int32_t scheme, int64_t ny, const double* y, int64_t ntheta,
+                             double* roots, double* poly, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

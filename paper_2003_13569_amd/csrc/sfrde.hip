@@ -27,6 +27,7 @@
 #include "coef.h"
 #include "kernels.h"
 #include "mfma.h"
+#include "stability.h"
 
 using namespace sfrde;
 
@@ -1405,6 +1406,39 @@ int sfrde_eval_coefficients(int32_t scheme, double L, double dt, int32_t deriv, 
     coef_derivs(scheme, L, dt, out6);
   else
     coef_values(scheme, L, dt, out6);
+  return SFRDE_OK;
+}
+
+int sfrde_amplification(int32_t scheme, int64_t count, const double* x, const double* y,
+                        double* r, void* hip_stream) {
+  g_err.clear();
+  if (scheme != SFRDE_SCHEME_P13 && scheme != SFRDE_SCHEME_EXP)
+    return fail(SFRDE_EINVAL, "unknown scheme %d", scheme);
+  if (count < 0 || count > (int64_t)1 << 36) return fail(SFRDE_EINVAL, "count out of range");
+  if (count == 0) return SFRDE_OK;
+  if (!x || !y || !r) return fail(SFRDE_EINVAL, "x, y and r must not be NULL");
+  const unsigned blocks = (unsigned)((count + 255) / 256);
+  hipLaunchKernelGGL(k_amplification, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                     (int)scheme, (long long)count, x, y, r);
+  HIPCHECK(hipGetLastError());
+  return SFRDE_OK;
+}
+
+int sfrde_stability_boundary(int32_t scheme, int64_t ny, const double* y, int64_t ntheta,
+                             double* roots, double* poly, void* hip_stream) {
+  g_err.clear();
+  if (scheme != SFRDE_SCHEME_P13 && scheme != SFRDE_SCHEME_EXP)
+    return fail(SFRDE_EINVAL, "unknown scheme %d", scheme);
+  if (ny < 0 || ntheta < 1 || ny > ((int64_t)1 << 30) || ntheta > ((int64_t)1 << 30) ||
+      ny * ntheta > ((int64_t)1 << 34))
+    return fail(SFRDE_EINVAL, "ny, ntheta out of range");
+  if (ny == 0) return SFRDE_OK;
+  if (!y || !roots) return fail(SFRDE_EINVAL, "y and roots must not be NULL");
+  const long long total = (long long)ny * ntheta;
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  hipLaunchKernelGGL(k_stability_boundary, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                     (int)scheme, (long long)ny, y, (long long)ntheta, roots, poly);
+  HIPCHECK(hipGetLastError());
   return SFRDE_OK;
 }
 

@@ -22,7 +22,7 @@ MAX_PARAMS = 16
 EXPORTS = ("sfrde_plan", "sfrde_step", "sfrde_integrate", "sfrde_ckpt_bytes", "sfrde_resume",
            "sfrde_backward", "sfrde_destroy", "sfrde_last_error", "sfrde_workspace_bytes",
            "sfrde_axis_eigenvalues", "sfrde_eval_coefficients", "sfrde_profile",
-           "sfrde_profile_read")
+           "sfrde_profile_read", "sfrde_amplification", "sfrde_stability_boundary")
 KERNEL_CLASSES = ("X", "Y", "Z", "XADJ", "ZADJ", "OTHER")
 
 
@@ -73,6 +73,10 @@ def lib() -> ctypes.CDLL:
     L.sfrde_axis_eigenvalues.restype = ctypes.c_int
     L.sfrde_eval_coefficients.argtypes = [i32, d, d, i32, pd]
     L.sfrde_eval_coefficients.restype = ctypes.c_int
+    L.sfrde_amplification.argtypes = [i32, i64, vp, vp, vp, vp]
+    L.sfrde_amplification.restype = ctypes.c_int
+    L.sfrde_stability_boundary.argtypes = [i32, i64, vp, i64, vp, vp, vp]
+    L.sfrde_stability_boundary.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -168,3 +172,16 @@ def sfrde_eval_coefficients(scheme, L, dt, deriv=False):
     _check(lib().sfrde_eval_coefficients(int(scheme), float(L), float(dt), int(bool(deriv)), out),
            "sfrde_eval_coefficients")
     return list(out)
+
+
+def sfrde_amplification(scheme, count, x, y, r, hip_stream=0) -> int:
+    """x, y, r: device addresses (x and r hold complex pairs)."""
+    return _check(lib().sfrde_amplification(int(scheme), int(count), x, y, r,
+                                            hip_stream or None), "sfrde_amplification")
+
+
+def sfrde_stability_boundary(scheme, ny, y, ntheta, roots, poly=None, hip_stream=0) -> int:
+    """y, roots, poly: device addresses (poly may be None)."""
+    return _check(lib().sfrde_stability_boundary(int(scheme), int(ny), y, int(ntheta), roots,
+                                                 poly, hip_stream or None),
+                  "sfrde_stability_boundary")

@@ -121,3 +121,31 @@ class SFRDEFunction(torch.autograd.Function):
         kd, ad, pd = ctx.param_dtypes
         return (gu0, torch.tensor(gk, dtype=kd), torch.tensor(ga, dtype=ad),
                 torch.tensor(gp if gp else [], dtype=pd), None)
+
+
+def amplification(x, y, scheme="p13"):
+    """Amplification factor r(x, y) of one step on the linear test equation
+    (Section 4.2.2) for complex128 CUDA tensors x and float64 y of one shape;
+    returns a complex128 tensor."""
+    x = x.to(torch.complex128).contiguous()
+    y = y.to(torch.float64).contiguous()
+    if not (x.is_cuda and y.is_cuda and x.shape == y.shape):
+        raise ValueError("x and y must be CUDA tensors of one shape")
+    r = torch.empty_like(x)
+    C.sfrde_amplification(C.SCHEME[scheme], x.numel(), x.data_ptr(), y.data_ptr(), r.data_ptr(),
+                          torch.cuda.current_stream().cuda_stream)
+    return r
+
+
+def stability_boundary(y, ntheta, scheme="p13"):
+    """Points of |r(x, y)| = 1 for each y in a float64 CUDA tensor:
+    (roots [ny, ntheta, 4] complex128, quartic coefficients [ny, 5])."""
+    y = y.to(torch.float64).contiguous()
+    if not y.is_cuda or y.dim() != 1:
+        raise ValueError("y must be a 1D CUDA tensor")
+    ny = y.numel()
+    roots = torch.empty((ny, ntheta, 4), dtype=torch.complex128, device=y.device)
+    poly = torch.empty((ny, 5), dtype=torch.float64, device=y.device)
+    C.sfrde_stability_boundary(C.SCHEME[scheme], ny, y.data_ptr(), ntheta, roots.data_ptr(),
+                               poly.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    return roots, poly

@@ -119,3 +119,15 @@ def test_host_coefficients_match_the_oracle(scheme):
             assert abs(got[q] - r) <= 2e-14 * max(abs(r), 1e-300) + 1e-300, (L, name, got[q], r)
             dr = dref[name][i]
             assert abs(dgot[q] - dr) <= 1e-11 * max(abs(dr), 1e-5), (L, name, dgot[q], dr)
+
+
+def test_stability_calls_validate_without_a_device():
+    L = C.lib()
+    assert L.sfrde_amplification(7, 4, None, None, None, None) == C.EINVAL
+    assert L.sfrde_amplification(0, -1, None, None, None, None) == C.EINVAL
+    assert L.sfrde_amplification(0, 4, None, None, None, None) == C.EINVAL
+    assert L.sfrde_amplification(1, 0, None, None, None, None) == C.OK
+    assert L.sfrde_stability_boundary(0, 2, None, 0, None, None, None) == C.EINVAL
+    assert L.sfrde_stability_boundary(0, 2, None, 8, None, None, None) == C.EINVAL
+    assert L.sfrde_stability_boundary(2, 2, None, 8, None, None, None) == C.EINVAL
+    assert L.sfrde_stability_boundary(0, 0, None, 8, None, None, None) == C.OK
