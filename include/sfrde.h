@@ -122,6 +122,21 @@ int sfrde_plan(sfrde_plan_t* out, int32_t ndim, const int64_t* n, int32_t bc,
                const double* kappa, double dt, int32_t reaction, int32_t nparams,
                const double* params, int32_t dtype, int32_t scheme, void* hip_stream);
 
+/* Ensemble plan: `batch` members (1..65535) of one grid, boundary
+ * condition, species count, time step, reaction kind, dtype and scheme, each
+ * with its own orders, diffusion coefficients and reaction parameters, all
+ * advanced by the same launches (the paper's parameter sweeps, Section 5.2).
+ *   alpha, kappa  [batch][nspecies]      params  [batch][nparams]
+ * Every other argument as in sfrde_plan, which is this call with batch = 1.
+ * With such a plan, state (and grad_uT, grad_u0) are [batch][S][...] device
+ * arrays; checkpoints hold every member; sfrde_backward's grad_kappa and
+ * grad_alpha are [batch][S] and grad_params [batch][nparams]. Members are
+ * independent: each computes what a plan of its own computes. */
+int sfrde_plan_batch(sfrde_plan_t* out, int32_t batch, int32_t ndim, const int64_t* n,
+                     int32_t bc, const double* h, int32_t nspecies, const double* alpha,
+                     const double* kappa, double dt, int32_t reaction, int32_t nparams,
+                     const double* params, int32_t dtype, int32_t scheme, void* hip_stream);
+
 /* One step from time t (eq. ETDRK4P13): state <- u(t + dt), in place.
  * state: device [S][...] of the plan's dtype. Same as sfrde_integrate with
  * nsteps = 1 and no checkpoints. */

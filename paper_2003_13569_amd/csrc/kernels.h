@@ -353,11 +353,54 @@ struct StageArgs {
   double* thp;        // adjoint Z kernels on L formed in the kernel: per-block kappa and
                       // alpha gradient partials [2 S][gridDim.x], accumulated (else G)
   int S;
+  // Ensembles: nmem members of one grid, launched together with
+  // blockIdx.y = member. Every per-member array is [member][...] with a
+  // member stride of fsz (= S total) times its per-member field count;
+  // rxm holds each member's reaction constants.
+  int nmem;
+  long long fsz;
+  const Rxn* rxm;
   int mode;         // stage 0..3, or MODE_INIT / MODE_RESTORE
   int last;         // adjoint: this is step 0 (output u-bar, not phi3 u-bar)
   int neumann;
   long long n0, n1, n2;
 };
+
+// v[s] for a run-time species index by selects, so that the kernel argument
+// block is never indexed dynamically (a modified copy of it would otherwise
+// be placed in scratch memory).
+template <typename T>
+__device__ __forceinline__ T pick_species(const T (&v)[MAX_SPECIES], int s) {
+  return s == 0 ? v[0] : s == 1 ? v[1] : s == 2 ? v[2] : v[3];
+}
+
+// Ensemble member of this block (blockIdx.y): offset every per-member array
+// and take the member's reaction constants. No-op for a single problem.
+template <typename T>
+__device__ __forceinline__ void to_member(StageArgs<T>& a) {
+  if (a.nmem <= 1) return;
+  const long long b = blockIdx.y;
+  const long long f = b * a.fsz;
+  a.P += f;
+  if (a.src) a.src += f;
+  if (a.coef) a.coef += NCOEF * f;
+  if (a.ltab) a.ltab += f;
+  if (a.dcoef) a.dcoef += NCOEF * f;
+  if (a.uhat) a.uhat += f;
+  if (a.ctil) a.ctil += f;
+  if (a.acc) a.acc += f;
+  if (a.zh) a.zh += f;
+  if (a.aacc) a.aacc += f;
+  if (a.ahat) a.ahat += f;
+  if (a.gu) a.gu += f;
+  if (a.G) a.G += f;
+  if (a.st_phys) a.st_phys += 4 * f;
+  if (a.st_uhat) a.st_uhat += f;
+  if (a.st_fhat) a.st_fhat += 4 * f;
+  if (a.rp_acc) a.rp_acc += b * MAX_PARAMS * gridDim.x;
+  if (a.thp) a.thp += b * 2 * a.S * gridDim.x;
+  a.rxn = a.rxm[b];
+}
 
 // ---------------------------------------------------------------- pointwise
 // Each phase walks the tile's elements in the coalescing order and works on
@@ -917,6 +960,7 @@ struct DenseXf {
 // X kernel, forward: inverse-x, reaction, forward-x (in place on P).
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_xstage(StageArgs<T> a) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   DenseXf<T> xf{&a.g, a.Mt};
   body_x<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
@@ -926,6 +970,7 @@ __global__ __launch_bounds__(NTHREADS) void k_xstage(StageArgs<T> a) {
 // inverse transform (in place on P).
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   DenseXf<T> xf{&a.g, a.Mt};
   body_z<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
@@ -935,6 +980,7 @@ __global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
 // transposed reaction Jacobian at the stored stage value, forward-x.
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   DenseXf<T> xf{&a.g, a.Mt};
   double pacc[RXN_NP_MAX];
@@ -949,6 +995,7 @@ __global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
 // Z kernel, adjoint: forward-z, adjoint combine, inverse-z.
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_zadj(StageArgs<T> a) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   DenseXf<T> xf{&a.g, a.Mt};
   body_zadj<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
@@ -965,12 +1012,23 @@ struct SingleArgs {
   int S;
   int pre_divide_w;
   int post_multiply_w;
-  int pad_;
+  int nmem;         // ensemble members (blockIdx.y), fields [member][S][total]
+  long long fsz;    // S total
   long long n0, n1, n2;
 };
 
+// Ensemble member of this block: offset the member's arrays (no-op for one).
+template <typename T>
+__device__ __forceinline__ void to_member(SingleArgs<T>& a) {
+  if (a.nmem <= 1) return;
+  const long long f = (long long)blockIdx.y * a.fsz;
+  a.src += f;
+  a.dst += f;
+}
+
 template <typename T>
 __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   const Geom& g = a.g;
@@ -1115,11 +1173,11 @@ __global__ void k_fill(T* p, long long n, T v) {
 
 // Checkpoint header: eight 64-bit words, lane i writes word i.
 __global__ void k_header(long long* h, long long a0, long long a1, long long a2, long long a3,
-                         long long a4, long long a5, long long a6, long long a7) {
+                         long long a4, long long a5, long long a6, long long a7, long long a8) {
   const int i = threadIdx.x;
   const long long v = i == 0 ? a0 : i == 1 ? a1 : i == 2 ? a2 : i == 3 ? a3
-                    : i == 4 ? a4 : i == 5 ? a5 : i == 6 ? a6 : a7;
-  if (blockIdx.x == 0 && i < 8) h[i] = v;
+                    : i == 4 ? a4 : i == 5 ? a5 : i == 6 ? a6 : i == 7 ? a7 : a8;
+  if (blockIdx.x == 0 && i < 9) h[i] = v;
 }
 
 }  // namespace sfrde

@@ -805,8 +805,8 @@ __device__ __forceinline__ void combine_pre(const StageArgs<float>& a, float* bu
     const float ly = three ? lam_lds[n0 + y] : 0.f;
 #pragma unroll
     for (int e = 0; e < 4; ++e) lxy[e] = lx[e] + ly;
-    kt = a.kt[s];
-    ha = a.ha[s];
+    kt = pick_species(a.kt, s);
+    ha = pick_species(a.ha, s);
   }
 #pragma unroll
   for (int k = 0; k < IO::MAXK; ++k) {
@@ -962,7 +962,7 @@ __device__ __forceinline__ void zadj_tile32(const StageArgs<float>& a, float* bu
     for (int e = 0; e < 4; ++e)
       wxy[e] = cs * wy * ((neu && (x0 + e == 0 || x0 + e == n0 - 1)) ? 0.5f : 1.f);
   }
-  const float kt = a.kt[s], ha = a.ha[s];
+  const float kt = pick_species(a.kt, s), ha = pick_species(a.ha, s);
   // per-tile sums in FP32 (at most 16 terms per thread), added in FP64
   float acc_k = 0.f, acc_a = 0.f;
 #pragma unroll
@@ -1250,6 +1250,7 @@ struct XFoldLoads {
 // last tile, the last one is loaded again and dropped.
 template <typename T, class XF, bool FAST>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(StageArgs<T> a, MfmaAxisDev ax) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
@@ -1319,6 +1320,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
 // computed. MODE < 0 takes a.mode at run time.
 template <typename T, class XF, int MODE, bool FAST>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(StageArgs<T> a, MfmaAxisDev ax) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
@@ -1378,6 +1380,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
 
 template <typename T, class XF, bool FAST>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(StageArgs<T> a, MfmaAxisDev ax) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
@@ -1434,6 +1437,7 @@ __device__ __forceinline__ void zadj_staged(const StageArgs<float>& a, float* bu
 // the kernel); MODE < 0 takes a.mode at run time.
 template <typename T, class XF, bool FAST, int MODE = -1>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(StageArgs<T> a, MfmaAxisDev ax) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
@@ -1512,6 +1516,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
 // point weights before (divide) or after (multiply).
 template <typename T, class XF, bool FAST>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(SingleArgs<T> a, MfmaAxisDev ax) {
+  to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));

@@ -61,6 +61,11 @@ int fail(int code, const char* fmt, ...) {
 
 const long long CKPT_MAGIC = 0x5346524445434b31LL;  // "SFRDECK1"
 constexpr int MAX_N = 1024;
+constexpr int MAX_BATCH = 65535;  // ensemble members: the launch's grid y extent
+// Reduction scratch of the backward pass: per-block partials first, then the
+// results of each ensemble member (2 S kappa/alpha sums, then parameters).
+constexpr long long RED_OUT = 2 * MAX_SPECIES * 1024 + 64;
+constexpr long long RED_PER_MEMBER = 2 * MAX_SPECIES + MAX_PARAMS;
 
 }  // namespace
 
@@ -70,10 +75,16 @@ struct sfrde_plan_s {
   int bc = 0;
   double h[3] = {1, 1, 1};
   int S = 0;
-  double alpha[MAX_SPECIES] = {0};
+  double alpha[MAX_SPECIES] = {0};  // member 0
   double kappa[MAX_SPECIES] = {0};
   double dt = 0;
   Rxn rxn{};
+  // ensembles: B members of this grid; per-member orders, coefficients and
+  // reaction constants ([B][S], [B])
+  int B = 1;
+  std::vector<double> alpha_m, kappa_m;
+  std::vector<Rxn> rxn_m;
+  Rxn* rxm = nullptr;  // device copy of rxn_m
   int dtype = 0;
   int scheme = 0;
   hipStream_t stream = nullptr;
@@ -127,7 +138,9 @@ struct sfrde_plan_s {
 
 namespace {
 
-size_t field_bytes(const sfrde_plan_s* p) { return (size_t)p->S * p->total * p->w; }
+// Elements and bytes of one field of every member: [B][S][total].
+size_t field_elems(const sfrde_plan_s* p) { return (size_t)p->B * p->S * p->total; }
+size_t field_bytes(const sfrde_plan_s* p) { return field_elems(p) * p->w; }
 
 int dev_alloc(sfrde_plan_s* p, void** ptr, size_t bytes) {
   if (*ptr) return SFRDE_OK;
@@ -426,7 +439,9 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   p->lds_m[axis] = lds;
   // persistent grid: as many blocks as fit on the CUs at once
   const long long per_cu = 1;
-  p->grid_m[axis] = (unsigned)std::min<long long>(g.ntiles, (long long)p->n_cu * per_cu);
+  // ensembles launch B times these blocks (blockIdx.y = member)
+  const long long slots = std::max<long long>(1, ((long long)p->n_cu * per_cu + p->B - 1) / p->B);
+  p->grid_m[axis] = (unsigned)std::min<long long>(g.ntiles, slots);
   // fragment-ordered split matrices
   if (p->dtype == SFRDE_F32) {
     std::vector<unsigned short> frag((size_t)MF_WAVES * MF_KSMAX_F32 * 2 * 64 * 8, 0);
@@ -521,6 +536,9 @@ StageArgs<T> stage_args(sfrde_plan_s* p, int axis, void* P) {
   a.gu = (T*)p->gu;
   a.flag = p->flag;
   a.rxn = p->rxn;
+  a.nmem = p->B;
+  a.fsz = (long long)p->S * p->total;
+  a.rxm = p->rxm;
   a.cs = T(p->cs);
   a.S = p->S;
   a.neumann = p->bc == SFRDE_BC_NEUMANN;
@@ -550,12 +568,14 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
   a.S = p->S;
   a.pre_divide_w = pre_div && p->bc == SFRDE_BC_NEUMANN;
   a.post_multiply_w = post_mul && p->bc == SFRDE_BC_NEUMANN;
+  a.nmem = p->B;
+  a.fsz = (long long)p->S * p->total;
   a.n0 = p->n[0];
   a.n1 = p->n[1];
   a.n2 = p->n[2];
   const long long pk = prof_start(p, KC_Y);
   if (p->use_m[axis]) {
-    const dim3 grid(p->grid_m[axis]);
+    const dim3 grid(p->grid_m[axis], p->B);
     const size_t lds = p->lds_m[axis];
     const bool fast = use_fast<T>(p, axis, {src, dst});
     if (axis == 0) {
@@ -580,8 +600,8 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
                          p->mfax[axis]);
     }
   } else
-    hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[axis],
-                       p->stream, a);
+    hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[axis], p->stream, a);
 launched:
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
@@ -591,17 +611,17 @@ launched:
 // Stored data of one step inside the segment store.
 template <typename T>
 struct StepStore {
-  T* phys;  // [4][S][total]
-  T* uhat;  // [S][total]
-  T* fhat;  // [4][S][total]
+  T* phys;  // [B][4][S][total]
+  T* uhat;  // [B][S][total]
+  T* fhat;  // [B][4][S][total]
 };
 
 template <typename T>
 StepStore<T> step_store(sfrde_plan_s* p, long long slot) {
   StepStore<T> s{nullptr, nullptr, nullptr};
   if (!p->seg) return s;
-  T* base = (T*)p->seg + (size_t)slot * 9 * p->S * p->total;
-  const size_t f = (size_t)p->S * p->total;
+  const size_t f = field_elems(p);
+  T* base = (T*)p->seg + (size_t)slot * 9 * f;
   s.phys = base;
   s.uhat = base + 4 * f;
   s.fhat = base + 5 * f;
@@ -616,7 +636,7 @@ int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
   a.st_phys = st_phys;
   const long long pk = prof_start(p, KC_X);
   if (p->use_m[0]) {
-    const dim3 grid(p->grid_m[0]), block(XfX<T>::THREADS);
+    const dim3 grid(p->grid_m[0], p->B), block(XfX<T>::THREADS);
     if (use_fast<T>(p, 0, {p->P, st_phys}))
       hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, std::is_same<T, float>::value>), grid, block,
                          p->lds_m[0], p->stream, a, p->mfax[0]);
@@ -624,8 +644,8 @@ int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
       hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
   } else
-    hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
-                       p->stream, a);
+    hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[0], p->stream, a);
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
@@ -666,12 +686,12 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat)
       // in the kernel or read from the table
       const bool staged = fast && p->n[ax] == 256 && mode >= 0 && mode <= 3 && !src &&
                           (p->lfly || p->ltab);
-      launch_zstage_m<T>(fast, staged ? mode : -1, dim3(p->grid_m[ax]), p->lds_m[ax], p->stream,
-                         a, p->mfax[ax]);
+      launch_zstage_m<T>(fast, staged ? mode : -1, dim3(p->grid_m[ax], p->B), p->lds_m[ax],
+                         p->stream, a, p->mfax[ax]);
     }
   else
-    hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
-                       p->stream, a);
+    hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[ax], p->stream, a);
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
@@ -726,17 +746,18 @@ int fill(sfrde_plan_s* p, T* ptr, long long n, T v) {
 int write_header(sfrde_plan_s* p, void* ckpt, long long nsteps, long long K) {
   hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, p->stream, (long long*)ckpt, CKPT_MAGIC,
                      nsteps, K, (long long)p->S, p->total, (long long)p->dtype,
-                     (long long)p->ndim, (long long)p->bc);
+                     (long long)p->ndim, (long long)p->bc, (long long)p->B);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
 }
 
 int check_header(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K) {
-  long long h[8];
+  long long h[9];
   HIPCHECK(hipMemcpyAsync(h, ckpt, sizeof(h), hipMemcpyDeviceToHost, p->stream));
   HIPCHECK(hipStreamSynchronize(p->stream));
   if (h[0] != CKPT_MAGIC) return fail(SFRDE_ESTATE, "checkpoint has no valid header");
-  if (h[3] != p->S || h[4] != p->total || h[5] != p->dtype || h[6] != p->ndim || h[7] != p->bc)
+  if (h[3] != p->S || h[4] != p->total || h[5] != p->dtype || h[6] != p->ndim || h[7] != p->bc ||
+      h[8] != p->B)
     return fail(SFRDE_ESTATE, "checkpoint was written by a plan of another shape/dtype");
   if (h[2] != K) return fail(SFRDE_ESTATE, "checkpoint spacing %lld != %lld", h[2], K);
   if (h[1] < nsteps) return fail(SFRDE_ESTATE, "checkpoint covers %lld < %lld steps", h[1], nsteps);
@@ -795,7 +816,7 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
   a.rp_acc = p->rp_acc;
   const long long pk = prof_start(p, KC_XADJ);
   if (p->use_m[0]) {
-    const dim3 grid(p->grid_m[0]), block(XfX<T>::THREADS);
+    const dim3 grid(p->grid_m[0], p->B), block(XfX<T>::THREADS);
     if (use_fast<T>(p, 0, {p->Pa}))
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, std::is_same<T, float>::value>), grid, block,
                          p->lds_m[0], p->stream, a, p->mfax[0]);
@@ -803,8 +824,8 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
   } else
-    hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[0],
-                       p->stream, a);
+    hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[0], p->stream, a);
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
@@ -825,7 +846,7 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
   if (!p->G) a.dcoef = nullptr;
   const long long pk = prof_start(p, KC_ZADJ);
   if (p->use_m[ax]) {
-    const dim3 grid(p->grid_m[ax]), block(XfZ<T>::THREADS);
+    const dim3 grid(p->grid_m[ax], p->B), block(XfZ<T>::THREADS);
     const size_t lds = p->lds_m[ax];
     const bool fast = use_fast<T>(p, ax, {p->Pa});
     // per-stage kernels: L formed in the kernel, no per-point accumulator
@@ -849,8 +870,8 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
       hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, false>), grid, block, p->lds_m[ax], p->stream, a,
                          p->mfax[ax]);
   } else
-    hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles), dim3(NTHREADS), p->lds[ax],
-                       p->stream, a);
+    hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[ax], p->stream, a);
 zadj_launched:
   prof_stop(p, pk);
   HIPCHECK(hipGetLastError());
@@ -866,6 +887,45 @@ int adjoint_step(sfrde_plan_s* p, const StepStore<T>& st, int last) {
     TRY(ypass<T>(p, p->Pa));
     TRY(launch_zadj<T>(p, m, &st, last));
     TRY(ypass<T>(p, p->Pa));
+  }
+  return SFRDE_OK;
+}
+
+// Coefficient arguments of member b (eigenvalue tables, kappa, alpha).
+CoefArgs coef_args(const sfrde_plan_s* p, int b, int deriv) {
+  CoefArgs c{};
+  c.lam0 = p->lam[0];
+  c.lam1 = p->lam[1];
+  c.lam2 = p->lam[2] ? p->lam[2] : p->lam[1];
+  c.n0 = p->n[0];
+  c.n1 = p->n[1];
+  c.n2 = p->n[2];
+  c.total = p->total;
+  c.S = p->S;
+  c.scheme = p->scheme;
+  c.deriv = deriv;
+  c.tau = p->dt;
+  for (int s = 0; s < p->S; ++s) {
+    c.alpha[s] = p->alpha_m[(size_t)b * p->S + s];
+    c.kappa[s] = p->kappa_m[(size_t)b * p->S + s];
+  }
+  return c;
+}
+
+// Per-point tables of every member, [B][k][S][total]: deriv 0 the six
+// coefficients (k = 6), 1 their d/dL (k = 6), 2 L itself (k = 1).
+int coef_tables(sfrde_plan_s* p, int deriv, void* out) {
+  const size_t per = (size_t)(deriv == 2 ? 1 : NCOEF) * p->S * p->total;
+  const long long blocks = std::min<long long>((p->total + NTHREADS - 1) / NTHREADS, 8192);
+  for (int b = 0; b < p->B; ++b) {
+    const CoefArgs c = coef_args(p, b, deriv);
+    if (p->dtype == SFRDE_F32)
+      hipLaunchKernelGGL(k_coefs<float>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
+                         (float*)out + b * per);
+    else
+      hipLaunchKernelGGL(k_coefs<double>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream,
+                         c, (double*)out + b * per);
+    HIPCHECK(hipGetLastError());
   }
   return SFRDE_OK;
 }
@@ -890,39 +950,17 @@ int ensure_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_thet
   if (want_theta && p->thp_on) {
     TRY(dev_alloc(p, (void**)&p->thp, (size_t)4 * p->grid_m[p->ndim - 1] * sizeof(double)));
   } else if (want_theta) {
-    TRY(dev_alloc(p, (void**)&p->G, (size_t)p->S * p->total * sizeof(double)));
+    TRY(dev_alloc(p, (void**)&p->G, field_elems(p) * sizeof(double)));
     if (!p->dcoef) {
       TRY(dev_alloc(p, &p->dcoef, NCOEF * f));
-      CoefArgs c{};
-      c.lam0 = p->lam[0];
-      c.lam1 = p->lam[1];
-      c.lam2 = p->lam[2] ? p->lam[2] : p->lam[1];
-      c.n0 = p->n[0];
-      c.n1 = p->n[1];
-      c.n2 = p->n[2];
-      c.total = p->total;
-      c.S = p->S;
-      c.scheme = p->scheme;
-      c.deriv = 1;
-      c.tau = p->dt;
-      for (int s = 0; s < p->S; ++s) {
-        c.alpha[s] = p->alpha[s];
-        c.kappa[s] = p->kappa[s];
-      }
-      long long blocks = std::min<long long>((p->total + NTHREADS - 1) / NTHREADS, 8192);
-      if (p->dtype == SFRDE_F32)
-        hipLaunchKernelGGL(k_coefs<float>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
-                           (float*)p->dcoef);
-      else
-        hipLaunchKernelGGL(k_coefs<double>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream,
-                           c, (double*)p->dcoef);
-      HIPCHECK(hipGetLastError());
+      TRY(coef_tables(p, 1, p->dcoef));
     }
   }
   if (want_p) {
-    TRY(dev_alloc(p, (void**)&p->rp_acc, (size_t)MAX_PARAMS * rp_blocks(p) * sizeof(double)));
+    TRY(dev_alloc(p, (void**)&p->rp_acc,
+                  (size_t)p->B * MAX_PARAMS * rp_blocks(p) * sizeof(double)));
   }
-  const long long need = 2 * MAX_SPECIES * 1024 + 64;
+  const long long need = RED_OUT + (long long)p->B * RED_PER_MEMBER;
   if (p->red && p->red_len < need) dev_free(p, (void**)&p->red, p->red_len * sizeof(double));
   if (!p->red) {
     TRY(dev_alloc(p, (void**)&p->red, need * sizeof(double)));
@@ -939,17 +977,18 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
   const long long seg_steps = std::min(K, nsteps);
   // kappa/alpha gradients formed inside the vector adjoint Z kernels (L
   // formed there too), else through the per-point accumulator G
-  p->thp_on = want_theta && p->lfly && p->S <= 2 && use_fast<T>(p, p->ndim - 1, {});
+  p->thp_on = want_theta && p->lfly && p->B == 1 && p->S <= 2 && use_fast<T>(p, p->ndim - 1, {});
   TRY(ensure_backward_buffers(p, seg_steps, want_theta, want_p));
   // Buffers from an earlier call stay allocated; accumulate only what is asked.
   double* G_saved = p->G;
   if (!want_theta || p->thp_on) p->G = nullptr;
-  if (p->G) TRY(fill<double>(p, p->G, (long long)p->S * p->total, 0.0));
+  if (p->G) TRY(fill<double>(p, p->G, (long long)field_elems(p), 0.0));
   const long long zgrid = p->grid_m[p->ndim - 1];
   if (p->thp_on) TRY(fill<double>(p, p->thp, 4 * zgrid, 0.0));
   double* rp_saved = p->rp_acc;
   if (!want_p) p->rp_acc = nullptr;
-  if (p->rp_acc) TRY(fill<double>(p, p->rp_acc, (long long)MAX_PARAMS * rp_blocks(p), 0.0));
+  if (p->rp_acc)
+    TRY(fill<double>(p, p->rp_acc, (long long)p->B * MAX_PARAMS * rp_blocks(p), 0.0));
 
   int rc = SFRDE_OK;
   do {
@@ -974,64 +1013,51 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
     if (rc) break;
     if (grad_u0 && (rc = launch_single<T>(p, 0, p->Pa, grad_u0, 0, 1))) break;
     const int nb = 1024;
-    double host[2 * MAX_SPECIES + MAX_PARAMS];
-    if (want_theta && p->thp_on) {
-      hipLaunchKernelGGL(k_rowsum, dim3(2 * p->S), dim3(NTHREADS), 0, p->stream, p->thp, zgrid,
-                         p->red + 2 * MAX_SPECIES * 1024);
-      if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
-      if (hipMemcpyAsync(host, p->red + 2 * MAX_SPECIES * 1024, 2 * p->S * sizeof(double),
-                         hipMemcpyDeviceToHost, p->stream) != hipSuccess) {
-        rc = fail(SFRDE_EDEVICE, "copy of gradient partials");
-        break;
+    double* rout = p->red + RED_OUT;
+    std::vector<double> host((size_t)p->B * RED_PER_MEMBER, 0.0);
+    for (int m = 0; m < p->B && rc == SFRDE_OK; ++m) {
+      double* ro = rout + (size_t)m * RED_PER_MEMBER;
+      if (want_theta && p->thp_on) {  // one member only (L formed in the kernels)
+        hipLaunchKernelGGL(k_rowsum, dim3(2 * p->S), dim3(NTHREADS), 0, p->stream, p->thp, zgrid,
+                           ro);
+        if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
+      } else if (want_theta) {
+        const CoefArgs c = coef_args(p, m, 0);
+        hipLaunchKernelGGL(k_greduce, dim3(nb), dim3(NTHREADS), 0, p->stream, c,
+                           p->G + (size_t)m * p->S * p->total, p->cs,
+                           (int)(p->bc == SFRDE_BC_NEUMANN), p->red);
+        if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_greduce launch"); break; }
+        hipLaunchKernelGGL(k_rowsum, dim3(2 * p->S), dim3(NTHREADS), 0, p->stream, p->red,
+                           (long long)nb, ro);
+        if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
       }
-    } else if (want_theta) {
-      CoefArgs c{};
-      c.lam0 = p->lam[0];
-      c.lam1 = p->lam[1];
-      c.lam2 = p->lam[2] ? p->lam[2] : p->lam[1];
-      c.n0 = p->n[0];
-      c.n1 = p->n[1];
-      c.n2 = p->n[2];
-      c.total = p->total;
-      c.S = p->S;
-      c.tau = p->dt;
-      for (int s = 0; s < p->S; ++s) {
-        c.alpha[s] = p->alpha[s];
-        c.kappa[s] = p->kappa[s];
-      }
-      hipLaunchKernelGGL(k_greduce, dim3(nb), dim3(NTHREADS), 0, p->stream, c, p->G, p->cs,
-                         (int)(p->bc == SFRDE_BC_NEUMANN), p->red);
-      if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_greduce launch"); break; }
-      hipLaunchKernelGGL(k_rowsum, dim3(2 * p->S), dim3(NTHREADS), 0, p->stream, p->red,
-                         (long long)nb, p->red + 2 * MAX_SPECIES * 1024);
-      if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
-      if (hipMemcpyAsync(host, p->red + 2 * MAX_SPECIES * 1024, 2 * p->S * sizeof(double),
-                         hipMemcpyDeviceToHost, p->stream) != hipSuccess) {
-        rc = fail(SFRDE_EDEVICE, "copy of gradient partials");
-        break;
+      if (want_p) {
+        hipLaunchKernelGGL(k_rowsum, dim3(p->rxn.np), dim3(NTHREADS), 0, p->stream,
+                           p->rp_acc + (size_t)m * MAX_PARAMS * rp_blocks(p), rp_blocks(p),
+                           ro + 2 * MAX_SPECIES);
+        if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
       }
     }
-    if (want_p) {
-      hipLaunchKernelGGL(k_rowsum, dim3(p->rxn.np), dim3(NTHREADS), 0, p->stream, p->rp_acc,
-                         rp_blocks(p), p->red + 2 * MAX_SPECIES * 1024 + 32);
-      if (hipGetLastError() != hipSuccess) { rc = fail(SFRDE_EDEVICE, "k_rowsum launch"); break; }
-      if (hipMemcpyAsync(host + 2 * MAX_SPECIES, p->red + 2 * MAX_SPECIES * 1024 + 32,
-                         p->rxn.np * sizeof(double), hipMemcpyDeviceToHost,
-                         p->stream) != hipSuccess) {
-        rc = fail(SFRDE_EDEVICE, "copy of parameter gradients");
-        break;
-      }
+    if (rc) break;
+    if ((want_theta || want_p) &&
+        hipMemcpyAsync(host.data(), rout, host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       p->stream) != hipSuccess) {
+      rc = fail(SFRDE_EDEVICE, "copy of gradient partials");
+      break;
     }
     if (hipStreamSynchronize(p->stream) != hipSuccess) {
       rc = fail(SFRDE_EDEVICE, "stream synchronize");
       break;
     }
-    for (int s = 0; s < p->S; ++s) {
-      if (gk) gk[s] = host[2 * s];
-      if (ga) ga[s] = host[2 * s + 1];
+    for (int m = 0; m < p->B; ++m) {
+      const double* hm = host.data() + (size_t)m * RED_PER_MEMBER;
+      for (int s = 0; s < p->S; ++s) {
+        if (gk) gk[m * p->S + s] = hm[2 * s];
+        if (ga) ga[m * p->S + s] = hm[2 * s + 1];
+      }
+      if (want_p)
+        for (int k = 0; k < p->rxn.np; ++k) gp[m * p->rxn.np + k] = hm[2 * MAX_SPECIES + k];
     }
-    if (want_p)
-      for (int k = 0; k < p->rxn.np; ++k) gp[k] = host[2 * MAX_SPECIES + k];
   } while (0);
   p->G = G_saved;
   p->rp_acc = rp_saved;
@@ -1045,7 +1071,7 @@ void destroy_plan(sfrde_plan_s* p) {
   void** ptrs[] = {&p->Mt[0], &p->Mt[1], &p->Mt[2], (void**)&p->lam[0], (void**)&p->lam[1],
                    (void**)&p->lam[2], &p->coef, &p->dcoef, &p->ltab, &p->P, &p->uhat, &p->ctil, &p->acc,
                    &p->Pa, &p->zh, &p->aacc, &p->ahat, &p->gu, (void**)&p->G, &p->seg,
-                   (void**)&p->rp_acc, (void**)&p->thp, (void**)&p->red, (void**)&p->flag, &p->mf_A[0],
+                   (void**)&p->rp_acc, (void**)&p->thp, (void**)&p->red, (void**)&p->flag, (void**)&p->rxm, &p->mf_A[0],
                    &p->mf_A[1], &p->mf_A[2]};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
@@ -1127,7 +1153,9 @@ int build_plan(sfrde_plan_s* p) {
     HIPCHECK(hipMemcpy(p->lam[a], lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   size_t lds_max = 0;
-  for (int a = 0; a < p->ndim; ++a) make_geom(p, a, 2LL * p->n_cu);
+  // dense tiles narrowed until the launch (all members) fills the device
+  for (int a = 0; a < p->ndim; ++a)
+    make_geom(p, a, std::max<long long>(1, (2LL * p->n_cu + p->B - 1) / p->B));
   for (int a = 0; a < p->ndim; ++a) TRY(setup_mfma_axis(p, a));
   {
     // FP32 P13 plans whose last axis runs the vector Z kernels form L there
@@ -1139,7 +1167,8 @@ int build_plan(sfrde_plan_s* p) {
     long long nsum = 0;
     for (int a = 0; a < p->ndim; ++a) nsum += p->n[a];
     const size_t extra = (size_t)nsum * sizeof(float);
-    if (p->dtype == SFRDE_F32 && p->scheme == SFRDE_SCHEME_P13 && !table && p->use_m[za] &&
+    if (p->dtype == SFRDE_F32 && p->scheme == SFRDE_SCHEME_P13 && !table && p->B == 1 &&
+        p->use_m[za] &&
         p->geom_m[za].fast && p->n[0] % 4 == 0 && p->lds_m[za] + extra <= 160 * 1024) {
       p->lfly = true;
       p->lam_off = (p->lds_m[za] + 15) / 16 * 16;
@@ -1162,43 +1191,18 @@ int build_plan(sfrde_plan_s* p) {
   TRY(dev_alloc(p, (void**)&p->flag, 64));
   HIPCHECK(hipHostMalloc((void**)&p->h_flag, sizeof(int), hipHostMallocDefault));
   *p->h_flag = 0;
-  CoefArgs c{};
-  c.lam0 = p->lam[0];
-  c.lam1 = p->lam[1];
-  c.lam2 = p->lam[2] ? p->lam[2] : p->lam[1];
-  c.n0 = p->n[0];
-  c.n1 = p->n[1];
-  c.n2 = p->n[2];
-  c.total = p->total;
-  c.S = p->S;
-  c.scheme = p->scheme;
-  c.deriv = 0;
-  c.tau = p->dt;
-  for (int s = 0; s < p->S; ++s) {
-    c.alpha[s] = p->alpha[s];
-    c.kappa[s] = p->kappa[s];
+  if (p->B > 1) {
+    TRY(dev_alloc(p, (void**)&p->rxm, p->rxn_m.size() * sizeof(Rxn)));
+    HIPCHECK(hipMemcpy(p->rxm, p->rxn_m.data(), p->rxn_m.size() * sizeof(Rxn),
+                       hipMemcpyHostToDevice));
   }
-  long long blocks = std::min<long long>((p->total + NTHREADS - 1) / NTHREADS, 8192);
-  if (p->dtype == SFRDE_F32)
-    hipLaunchKernelGGL(k_coefs<float>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
-                       (float*)p->coef);
-  else
-    hipLaunchKernelGGL(k_coefs<double>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
-                       (double*)p->coef);
-  HIPCHECK(hipGetLastError());
+  TRY(coef_tables(p, 0, p->coef));
   if (p->scheme == SFRDE_SCHEME_P13) {
     // The forward combine forms the P13 coefficients from L: one table read
     // per species and stage instead of up to four. The six tables stay for
     // the adjoint.
     TRY(dev_alloc(p, &p->ltab, f));
-    c.deriv = 2;
-    if (p->dtype == SFRDE_F32)
-      hipLaunchKernelGGL(k_coefs<float>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream, c,
-                         (float*)p->ltab);
-    else
-      hipLaunchKernelGGL(k_coefs<double>, dim3((unsigned)blocks), dim3(NTHREADS), 0, p->stream,
-                         c, (double*)p->ltab);
-    HIPCHECK(hipGetLastError());
+    TRY(coef_tables(p, 2, p->ltab));
   }
   TRY(fill<int>(p, p->flag, 16, 0));
   HIPCHECK(hipStreamSynchronize(p->stream));
@@ -1212,15 +1216,21 @@ extern "C" {
 
 const char* sfrde_last_error(void) { return g_err.c_str(); }
 
-int sfrde_plan(sfrde_plan_t* out, int32_t ndim, const int64_t* n, int32_t bc, const double* h,
-               int32_t nspecies, const double* alpha, const double* kappa, double dt,
-               int32_t reaction, int32_t nparams, const double* params, int32_t dtype,
-               int32_t scheme, void* hip_stream) {
+int sfrde_plan_batch(sfrde_plan_t* out, int32_t batch, int32_t ndim, const int64_t* n,
+                     int32_t bc, const double* h, int32_t nspecies, const double* alpha,
+                     const double* kappa, double dt, int32_t reaction, int32_t nparams,
+                     const double* params, int32_t dtype, int32_t scheme, void* hip_stream) {
   g_err.clear();
   if (!out) return fail(SFRDE_EINVAL, "out must not be NULL");
   *out = nullptr;
-  TRY(validate(ndim, n, bc, h, nspecies, alpha, kappa, dt, reaction, nparams, params, dtype,
-               scheme));
+  if (batch < 1 || batch > MAX_BATCH)
+    return fail(SFRDE_EINVAL, "batch %d outside [1, %d]", batch, MAX_BATCH);
+  if (!alpha || !kappa) return fail(SFRDE_EINVAL, "alpha and kappa must not be NULL");
+  if (nparams > 0 && !params) return fail(SFRDE_EINVAL, "params must not be NULL");
+  for (int b = 0; b < batch; ++b)
+    TRY(validate(ndim, n, bc, h, nspecies, alpha + (size_t)b * nspecies,
+                 kappa + (size_t)b * nspecies, dt, reaction, nparams,
+                 params ? params + (size_t)b * nparams : nullptr, dtype, scheme));
   sfrde_plan_s* p = new (std::nothrow) sfrde_plan_s();
   if (!p) return fail(SFRDE_ENOMEM, "host allocation of the plan failed");
   // A 1D plan runs as a 2D one whose second axis has one point (eigenvalue
@@ -1239,32 +1249,42 @@ int sfrde_plan(sfrde_plan_t* out, int32_t ndim, const int64_t* n, int32_t bc, co
   }
   p->bc = bc;
   p->S = nspecies;
+  p->B = batch;
+  p->alpha_m.assign(alpha, alpha + (size_t)batch * nspecies);
+  p->kappa_m.assign(kappa, kappa + (size_t)batch * nspecies);
   for (int s = 0; s < nspecies; ++s) {
     p->alpha[s] = alpha[s];
     p->kappa[s] = kappa[s];
   }
   p->dt = dt;
-  p->rxn.kind = reaction;
-  p->rxn.S = nspecies;
-  p->rxn.np = nparams;
-  for (int k = 0; k < nparams; ++k) p->rxn.p[k] = params[k];
-  if (reaction >= RXN_HUXLEY_MMS) {
-    // source constants of Examples 1 and 2 (Section 5.1), see mms_source()
-    const double pi = 3.14159265358979323846, a = alpha[0], k = kappa[0];
-    double* c = p->rxn.p + MMS_P0;
-    c[0] = a;
-    if (reaction == RXN_HUXLEY_MMS) {
-      c[1] = k / 16.0 * 9.0 * pow(8.0 * pi * pi, 0.5 * a);
-      c[2] = k / 16.0 * 3.0 * pow(40.0 * pi * pi, 0.5 * a);
-      c[3] = k / 16.0 * pow(72.0 * pi * pi, 0.5 * a);
-    } else {
-      c[1] = k / 4.0 * 3.0 * pow(2.0 * pi, a);
-      c[2] = 0.0;
-      c[3] = k / 4.0 * pow(6.0 * pi, a);
+  p->rxn_m.resize(batch);
+  for (int b = 0; b < batch; ++b) {
+    Rxn& r = p->rxn_m[b];
+    r = Rxn{};
+    r.kind = reaction;
+    r.S = nspecies;
+    r.np = nparams;
+    for (int k = 0; k < nparams; ++k) r.p[k] = params[(size_t)b * nparams + k];
+    if (reaction >= RXN_HUXLEY_MMS) {
+      // source constants of Examples 1 and 2 (Section 5.1), see mms_source()
+      const double pi = 3.14159265358979323846, a = alpha[(size_t)b * nspecies],
+                   k = kappa[(size_t)b * nspecies];
+      double* c = r.p + MMS_P0;
+      c[0] = a;
+      if (reaction == RXN_HUXLEY_MMS) {
+        c[1] = k / 16.0 * 9.0 * pow(8.0 * pi * pi, 0.5 * a);
+        c[2] = k / 16.0 * 3.0 * pow(40.0 * pi * pi, 0.5 * a);
+        c[3] = k / 16.0 * pow(72.0 * pi * pi, 0.5 * a);
+      } else {
+        c[1] = k / 4.0 * 3.0 * pow(2.0 * pi, a);
+        c[2] = 0.0;
+        c[3] = k / 4.0 * pow(6.0 * pi, a);
+      }
+      c[4] = h[0];
+      c[5] = ndim > 1 ? h[1] : 0.0;
     }
-    c[4] = h[0];
-    c[5] = ndim > 1 ? h[1] : 0.0;
   }
+  p->rxn = p->rxn_m[0];
   p->dtype = dtype;
   p->scheme = scheme;
   p->stream = (hipStream_t)hip_stream;
@@ -1279,6 +1299,14 @@ int sfrde_plan(sfrde_plan_t* out, int32_t ndim, const int64_t* n, int32_t bc, co
   }
   *out = p;
   return SFRDE_OK;
+}
+
+int sfrde_plan(sfrde_plan_t* out, int32_t ndim, const int64_t* n, int32_t bc, const double* h,
+               int32_t nspecies, const double* alpha, const double* kappa, double dt,
+               int32_t reaction, int32_t nparams, const double* params, int32_t dtype,
+               int32_t scheme, void* hip_stream) {
+  return sfrde_plan_batch(out, 1, ndim, n, bc, h, nspecies, alpha, kappa, dt, reaction, nparams,
+                          params, dtype, scheme, hip_stream);
 }
 
 int sfrde_destroy(sfrde_plan_t plan) {
@@ -1320,10 +1348,11 @@ int sfrde_resume(sfrde_plan_t p, const void* ckpt, int64_t slot, void* state, in
   if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
   if (!ckpt || !state) return fail(SFRDE_EINVAL, "ckpt and state must not be NULL");
   if (slot < 0 || nsteps < 0 || ckpt_every < 0) return fail(SFRDE_EINVAL, "negative argument");
-  long long h[8];
+  long long h[9];
   HIPCHECK(hipMemcpyAsync(h, ckpt, sizeof(h), hipMemcpyDeviceToHost, p->stream));
   HIPCHECK(hipStreamSynchronize(p->stream));
-  if (h[0] != CKPT_MAGIC || h[3] != p->S || h[4] != p->total || h[5] != p->dtype)
+  if (h[0] != CKPT_MAGIC || h[3] != p->S || h[4] != p->total || h[5] != p->dtype ||
+      h[8] != p->B)
     return fail(SFRDE_ESTATE, "checkpoint does not match this plan");
   const long long nslots = (h[1] + h[2] - 1) / h[2];
   if (slot >= nslots) return fail(SFRDE_ESTATE, "slot %lld >= %lld slots", (long long)slot, nslots);

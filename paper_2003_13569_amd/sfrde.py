@@ -19,7 +19,7 @@ REACTION = {"linear": 0, "fhn": 1, "gray_scott": 2, "schnakenberg": 3, "gierer_m
 CKPT_HEADER_BYTES = 256
 MAX_PARAMS = 16
 
-EXPORTS = ("sfrde_plan", "sfrde_step", "sfrde_integrate", "sfrde_ckpt_bytes", "sfrde_resume",
+EXPORTS = ("sfrde_plan", "sfrde_plan_batch", "sfrde_step", "sfrde_integrate", "sfrde_ckpt_bytes", "sfrde_resume",
            "sfrde_backward", "sfrde_destroy", "sfrde_last_error", "sfrde_workspace_bytes",
            "sfrde_axis_eigenvalues", "sfrde_eval_coefficients", "sfrde_profile",
            "sfrde_profile_read", "sfrde_amplification", "sfrde_stability_boundary")
@@ -49,6 +49,9 @@ def lib() -> ctypes.CDLL:
     L.sfrde_plan.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(i64), i32, pd, i32, pd, pd, d,
                              i32, i32, pd, i32, i32, vp]
     L.sfrde_plan.restype = ctypes.c_int
+    L.sfrde_plan_batch.argtypes = [ctypes.POINTER(vp), i32, i32, ctypes.POINTER(i64), i32, pd,
+                                   i32, pd, pd, d, i32, i32, pd, i32, i32, vp]
+    L.sfrde_plan_batch.restype = ctypes.c_int
     L.sfrde_step.argtypes = [vp, vp, d]
     L.sfrde_step.restype = ctypes.c_int
     L.sfrde_integrate.argtypes = [vp, vp, i64, d, i64, vp]
@@ -109,6 +112,21 @@ def sfrde_plan(ndim, n, bc, h, nspecies, alpha, kappa, dt, reaction, nparams, pa
     return out.value
 
 
+def sfrde_plan_batch(batch, ndim, n, bc, h, nspecies, alpha, kappa, dt, reaction, nparams,
+                     params, dtype, scheme, hip_stream=0) -> int:
+    """Ensemble plan; alpha, kappa are [batch][nspecies] and params [batch][nparams],
+    flattened. Returns the handle."""
+    out = ctypes.c_void_p()
+    n_arr = (ctypes.c_int64 * max(1, len(n)))(*[int(v) for v in n])
+    rc = lib().sfrde_plan_batch(ctypes.byref(out), int(batch), int(ndim), n_arr, int(bc),
+                                _darr(h), int(nspecies), _darr(alpha), _darr(kappa), float(dt),
+                                int(reaction), int(nparams), _darr(params), int(dtype),
+                                int(scheme),
+                                ctypes.c_void_p(int(hip_stream) if hip_stream else None))
+    _check(rc, "sfrde_plan_batch")
+    return out.value
+
+
 def sfrde_step(plan, state, t) -> int:
     return _check(lib().sfrde_step(plan, state, float(t)), "sfrde_step")
 
@@ -128,16 +146,18 @@ def sfrde_resume(plan, ckpt, slot, state, nsteps, t0, ckpt_every=0, ckpt_out=Non
 
 
 def sfrde_backward(plan, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0=None, nspecies=2,
-                   nparams=0, want_kappa=True, want_alpha=True, want_params=True):
-    """Returns (grad_kappa, grad_alpha, grad_params) as lists (None if not asked)."""
-    gk = (ctypes.c_double * nspecies)() if want_kappa else None
-    ga = (ctypes.c_double * nspecies)() if want_alpha else None
-    gp = (ctypes.c_double * max(1, nparams))() if (want_params and nparams > 0) else None
+                   nparams=0, want_kappa=True, want_alpha=True, want_params=True, batch=1):
+    """Returns (grad_kappa, grad_alpha, grad_params) as flat lists, [batch][...]
+    for ensemble plans (None if not asked)."""
+    gk = (ctypes.c_double * (batch * nspecies))() if want_kappa else None
+    ga = (ctypes.c_double * (batch * nspecies))() if want_alpha else None
+    gp = ((ctypes.c_double * max(1, batch * nparams))() if (want_params and nparams > 0)
+          else None)
     rc = lib().sfrde_backward(plan, ckpt, int(nsteps), int(ckpt_every), float(t0), grad_uT,
                               grad_u0, gk, ga, gp)
     _check(rc, "sfrde_backward")
     return (list(gk) if gk is not None else None, list(ga) if ga is not None else None,
-            list(gp)[:nparams] if gp is not None else None)
+            list(gp)[:batch * nparams] if gp is not None else None)
 
 
 def sfrde_destroy(plan) -> int:

@@ -13,34 +13,53 @@ _TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64}
 
 
 class Plan:
-    """A libsfrde plan for fields shaped ``[S, (nz,) ny, nx]``.
+    """A libsfrde plan for fields shaped ``[S, (nz,) ny, nx]``, or an ensemble
+    plan (``batch`` members, fields ``[batch, S, ...]``) when ``batch`` is given:
+    then ``alpha`` and ``kappa`` are ``[batch][S]`` and ``params`` ``[batch][np]``.
 
     ``shape`` and ``h`` are in tensor order (slowest axis first); the C ABI
     takes them x-first, which this wrapper handles.
     """
 
     def __init__(self, shape, bc, h, alpha, kappa, dt, reaction, params, dtype="f32",
-                 scheme="p13", stream=None):
+                 scheme="p13", stream=None, batch=None):
         self.shape = tuple(int(v) for v in shape)
         self.ndim = len(self.shape)
-        self.S = len(alpha)
+        self.batch = batch
         self.dtype = dtype
         self.torch_dtype = _TORCH_DTYPE[dtype]
         self.dt = float(dt)
-        self.nparams = len(params)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
-        self.handle = C.sfrde_plan(self.ndim, list(reversed(self.shape)), C.BC[bc],
-                                   list(reversed(list(h))), self.S, alpha, kappa, dt,
-                                   C.REACTION[reaction], len(params), params, C.DTYPE[dtype],
-                                   C.SCHEME[scheme], stream.cuda_stream)
+        n_xyz, h_xyz = list(reversed(self.shape)), list(reversed(list(h)))
+        if batch is None:
+            self.S = len(alpha)
+            self.nparams = len(params)
+            self.handle = C.sfrde_plan(self.ndim, n_xyz, C.BC[bc], h_xyz, self.S, alpha, kappa,
+                                       dt, C.REACTION[reaction], len(params), params,
+                                       C.DTYPE[dtype], C.SCHEME[scheme], stream.cuda_stream)
+        else:
+            if not (len(alpha) == len(kappa) == len(params) == batch):
+                raise ValueError("alpha, kappa and params need one entry per member")
+            self.S = len(alpha[0])
+            self.nparams = len(params[0])
+            flat = lambda rows: [float(v) for r in rows for v in r]  # noqa: E731
+            self.handle = C.sfrde_plan_batch(batch, self.ndim, n_xyz, C.BC[bc], h_xyz, self.S,
+                                             flat(alpha), flat(kappa), dt, C.REACTION[reaction],
+                                             self.nparams, flat(params), C.DTYPE[dtype],
+                                             C.SCHEME[scheme], stream.cuda_stream)
+
+    @property
+    def field_shape(self):
+        lead = (self.S,) if self.batch is None else (self.batch, self.S)
+        return lead + self.shape
 
     def _check_field(self, u):
         if not (u.is_cuda and u.is_contiguous() and u.dtype == self.torch_dtype
-                and tuple(u.shape) == (self.S,) + self.shape):
+                and tuple(u.shape) == self.field_shape):
             raise ValueError(f"expected a contiguous {self.torch_dtype} CUDA tensor of shape "
-                             f"{(self.S,) + self.shape}, got {u.dtype} {tuple(u.shape)}")
+                             f"{self.field_shape}, got {u.dtype} {tuple(u.shape)}")
 
     def ckpt_bytes(self, nsteps, ckpt_every):
         return C.sfrde_ckpt_bytes(self.handle, nsteps, ckpt_every)
@@ -75,7 +94,7 @@ class Plan:
         return C.sfrde_backward(self.handle, ckpt.data_ptr(), nsteps, ckpt_every, t0,
                                 grad_uT.data_ptr(),
                                 grad_u0.data_ptr() if grad_u0 is not None else None,
-                                self.S, self.nparams, kappa, alpha, params)
+                                self.S, self.nparams, kappa, alpha, params, self.batch or 1)
 
     def workspace_bytes(self):
         return C.sfrde_workspace_bytes(self.handle)
