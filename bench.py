@@ -144,6 +144,9 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--ensemble-members", type=int, default=64)
+    ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (PMC scaling)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH",
@@ -308,6 +311,41 @@ def main() -> int:
         print(f"[bench] adjoint/forward = {t_bwd / t_fwd:.2f}", flush=True)
         del ckpt, g, g0
 
+    # ---------------------------------------------------------------- ensemble
+    # The small 2D FitzHugh-Nagumo problem (64x64, FP64) alone and as B
+    # members with orders spread over [1.2, 2.0] in one ensemble plan.
+    ensemble = None
+    if not args.no_ensemble:
+        e = W.C1_FHN
+        B, ke = args.ensemble_members, args.ensemble_steps
+        e0 = W.initial_fields(e)
+        single = Plan(e.shape, e.bc, e.h, e.alpha, e.kappa, e.dt, e.reaction, e.params, "f64")
+        alphas = [(a, a) for a in np.linspace(1.2, 2.0, B)]
+        batch = Plan(e.shape, e.bc, e.h, alphas, [e.kappa] * B, e.dt, e.reaction,
+                     [e.params] * B, "f64", batch=B)
+
+        def run_timed(plan, u):
+            w = u.clone()
+            plan.integrate(w, 2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.integrate(u, ke)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / ke
+
+        ms1 = run_timed(single, torch.tensor(e0, device="cuda"))
+        msb = run_timed(batch, torch.tensor(np.stack([e0] * B), device="cuda"))
+        ensemble = {"workload": f"{e.name} x {B} members (alpha 1.2..2.0)", "dtype": "f64",
+                    "steps": ke, "single_ms_per_step": round(ms1, 4),
+                    "batch_ms_per_step": round(msb, 4),
+                    "member_steps_per_s_single": round(1e3 / ms1, 1),
+                    "member_steps_per_s_batch": round(B * 1e3 / msb, 1),
+                    "speedup_vs_one_at_a_time": round(B * ms1 / msb, 2)}
+        print(f"[bench] ensemble: single {ms1:.3f} ms/step, {B} members {msb:.3f} ms/step "
+              f"({B * ms1 / msb:.1f}x)", flush=True)
+        single.close()
+        batch.close()
+
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
@@ -348,6 +386,7 @@ def main() -> int:
         "fp64": fp64,
         "error": {"fp32_vs_fp64_gpu": err, "steps": args.fp64_steps} if err is not None else None,
         "adjoint": adjoint,
+        "ensemble": ensemble,
         "roofline": roofline,
         "step_effective_gbs": round(step_gbs, 1),
         "kernels": kernels,

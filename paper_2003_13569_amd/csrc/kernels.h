@@ -957,32 +957,41 @@ struct DenseXf {
   __device__ __forceinline__ void operator()(T* buf, int S) { dense_transform(buf, S, *g, Mt); }
 };
 
-// X kernel, forward: inverse-x, reaction, forward-x (in place on P).
+// No transform: the kernels below then do only their pointwise part, for
+// axes whose transforms run as library matrix products around them.
 template <typename T>
+struct NoXf {
+  const Geom* g;
+  const T* Mt;
+  __device__ __forceinline__ void operator()(T*, int) {}
+};
+
+// X kernel, forward: inverse-x, reaction, forward-x (in place on P).
+template <typename T, template <typename> class XFT = DenseXf>
 __global__ __launch_bounds__(NTHREADS) void k_xstage(StageArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  DenseXf<T> xf{&a.g, a.Mt};
+  XFT<T> xf{&a.g, a.Mt};
   body_x<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
 }
 
 // Z kernel, forward: forward transform along the last axis, stage combine,
 // inverse transform (in place on P).
-template <typename T>
+template <typename T, template <typename> class XFT = DenseXf>
 __global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  DenseXf<T> xf{&a.g, a.Mt};
+  XFT<T> xf{&a.g, a.Mt};
   body_z<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
 }
 
 // X kernel, adjoint: inverse-x of the spectral cotangent of f(stage value),
 // transposed reaction Jacobian at the stored stage value, forward-x.
-template <typename T>
+template <typename T, template <typename> class XFT = DenseXf>
 __global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  DenseXf<T> xf{&a.g, a.Mt};
+  XFT<T> xf{&a.g, a.Mt};
   double pacc[RXN_NP_MAX];
   for (int k = 0; k < RXN_NP_MAX; ++k) pacc[k] = 0.0;
   body_xadj<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf, pacc);
@@ -993,11 +1002,11 @@ __global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
 }
 
 // Z kernel, adjoint: forward-z, adjoint combine, inverse-z.
-template <typename T>
+template <typename T, template <typename> class XFT = DenseXf>
 __global__ __launch_bounds__(NTHREADS) void k_zadj(StageArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  DenseXf<T> xf{&a.g, a.Mt};
+  XFT<T> xf{&a.g, a.Mt};
   body_zadj<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
 }
 
@@ -1026,7 +1035,7 @@ __device__ __forceinline__ void to_member(SingleArgs<T>& a) {
   a.dst += f;
 }
 
-template <typename T>
+template <typename T, template <typename> class XFT = DenseXf>
 __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1048,7 +1057,7 @@ __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
     }
     __syncthreads();
   }
-  dense_transform(buf, a.S, g, a.Mt);
+  XFT<T>{&g, a.Mt}(buf, a.S);
   if (a.post_multiply_w) {
     for (int e = threadIdx.x; e < ne; e += blockDim.x) {
       int j, w;

@@ -9,6 +9,7 @@
 // adjoint buffers, a segment store for recomputed stage data and the
 // derivative tables.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -95,6 +96,11 @@ struct sfrde_plan_s {
   size_t lds[3] = {0, 0, 0};
   // matrix-core variant per axis (see mfma.h)
   bool use_m[3] = {false, false, false};
+  // axes too long for the matrix-core engine: transforms as library matrix
+  // products (rocBLAS) around pointwise-only tile kernels, through gtmp
+  bool use_g[3] = {false, false, false};
+  rocblas_handle blas = nullptr;
+  void* gtmp = nullptr;
   Geom geom_m[3]{};
   size_t lds_m[3] = {0, 0, 0};
   unsigned grid_m[3] = {0, 0, 0};
@@ -558,6 +564,45 @@ bool use_fast(const sfrde_plan_s* p, int axis, std::initializer_list<const void*
   return true;
 }
 
+// Transform along `axis` of every field of the plan as a library matrix
+// product, src -> dst (not aliased). With M the axis matrix (column-major, as
+// the transposed table Mt is stored):
+//   x axis (contiguous lines):  dst (n x lines) = M src (n x lines)
+//   strided axis, per block o of n*inner points: dst_o (inner x n) = src_o (inner x n) M^T
+template <typename T>
+int gemm_axis(sfrde_plan_s* p, int axis, const T* src, T* dst) {
+  const long long n = p->n[axis];
+  long long inner = 1;
+  for (int a = 0; a < axis; ++a) inner *= p->n[a];
+  const long long elems = (long long)field_elems(p);
+  const long long cols = elems / n;  // lines (x) or outer blocks times inner
+  if (cols > INT32_MAX || n > INT32_MAX) return fail(SFRDE_EUNSUPPORTED, "field too large for rocBLAS");
+  const T one = T(1), zero = T(0);
+  const T* M = (const T*)p->Mt[axis];
+  rocblas_status st;
+  if (inner == 1) {
+    if constexpr (std::is_same<T, float>::value)
+      st = rocblas_sgemm(p->blas, rocblas_operation_none, rocblas_operation_none, (int)n, (int)cols,
+                         (int)n, &one, M, (int)n, src, (int)n, &zero, dst, (int)n);
+    else
+      st = rocblas_dgemm(p->blas, rocblas_operation_none, rocblas_operation_none, (int)n, (int)cols,
+                         (int)n, &one, M, (int)n, src, (int)n, &zero, dst, (int)n);
+  } else {
+    const long long batch = elems / (n * inner);
+    if (batch > INT32_MAX) return fail(SFRDE_EUNSUPPORTED, "field too large for rocBLAS");
+    if constexpr (std::is_same<T, float>::value)
+      st = rocblas_sgemm_strided_batched(p->blas, rocblas_operation_none, rocblas_operation_transpose,
+                                         (int)inner, (int)n, (int)n, &one, src, (int)inner, n * inner,
+                                         M, (int)n, 0, &zero, dst, (int)inner, n * inner, (int)batch);
+    else
+      st = rocblas_dgemm_strided_batched(p->blas, rocblas_operation_none, rocblas_operation_transpose,
+                                         (int)inner, (int)n, (int)n, &one, src, (int)inner, n * inner,
+                                         M, (int)n, 0, &zero, dst, (int)inner, n * inner, (int)batch);
+  }
+  if (st != rocblas_status_success) return fail(SFRDE_EDEVICE, "rocBLAS gemm failed (%d)", (int)st);
+  return SFRDE_OK;
+}
+
 template <typename T>
 int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre_div, int post_mul) {
   SingleArgs<T> a{};
@@ -598,6 +643,25 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
         }
       hipLaunchKernelGGL((k_single_m<T, XfZ<T>, false>), grid, block, lds, p->stream, a,
                          p->mfax[axis]);
+    }
+  } else if (p->use_g[axis]) {
+    // library product through gtmp; the weights (or a copy) in a pointwise pass
+    T* tmp = (T*)p->gtmp;
+    const dim3 grid((unsigned)a.g.ntiles, p->B);
+    if (!a.pre_divide_w && !a.post_multiply_w && src != dst) {
+      TRY(gemm_axis<T>(p, axis, (const T*)src, (T*)dst));
+    } else if (a.pre_divide_w) {
+      SingleArgs<T> w = a;
+      w.dst = tmp;
+      w.post_multiply_w = 0;
+      hipLaunchKernelGGL((k_single<T, NoXf>), grid, dim3(NTHREADS), p->lds[axis], p->stream, w);
+      HIPCHECK(hipGetLastError());
+      TRY(gemm_axis<T>(p, axis, tmp, (T*)dst));
+    } else {
+      TRY(gemm_axis<T>(p, axis, (const T*)src, tmp));
+      SingleArgs<T> w = a;
+      w.src = tmp;
+      hipLaunchKernelGGL((k_single<T, NoXf>), grid, dim3(NTHREADS), p->lds[axis], p->stream, w);
     }
   } else
     hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
@@ -643,6 +707,15 @@ int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
     else
       hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
+  } else if (p->use_g[0]) {
+    T* tmp = (T*)p->gtmp;
+    TRY(gemm_axis<T>(p, 0, a.P, tmp));
+    StageArgs<T> b = a;
+    b.P = tmp;
+    hipLaunchKernelGGL((k_xstage<T, NoXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[0], p->stream, b);
+    HIPCHECK(hipGetLastError());
+    TRY(gemm_axis<T>(p, 0, tmp, a.P));
   } else
     hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
                        p->lds[0], p->stream, a);
@@ -689,7 +762,17 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat)
       launch_zstage_m<T>(fast, staged ? mode : -1, dim3(p->grid_m[ax], p->B), p->lds_m[ax],
                          p->stream, a, p->mfax[ax]);
     }
-  else
+  else if (p->use_g[ax]) {
+    // a spectral source is read by the pointwise pass itself
+    T* tmp = (T*)p->gtmp;
+    if (!src) TRY(gemm_axis<T>(p, ax, a.P, tmp));
+    StageArgs<T> b = a;
+    b.P = tmp;
+    hipLaunchKernelGGL((k_zstage<T, NoXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[ax], p->stream, b);
+    HIPCHECK(hipGetLastError());
+    TRY(gemm_axis<T>(p, ax, tmp, a.P));
+  } else
     hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
                        p->lds[ax], p->stream, a);
   prof_stop(p, pk);
@@ -823,6 +906,15 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
     else
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
+  } else if (p->use_g[0]) {
+    T* tmp = (T*)p->gtmp;
+    TRY(gemm_axis<T>(p, 0, a.P, tmp));
+    StageArgs<T> b = a;
+    b.P = tmp;
+    hipLaunchKernelGGL((k_xadj<T, NoXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[0], p->stream, b);
+    HIPCHECK(hipGetLastError());
+    TRY(gemm_axis<T>(p, 0, tmp, a.P));
   } else
     hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
                        p->lds[0], p->stream, a);
@@ -869,6 +961,15 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
     else
       hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, false>), grid, block, p->lds_m[ax], p->stream, a,
                          p->mfax[ax]);
+  } else if (p->use_g[ax]) {
+    T* tmp = (T*)p->gtmp;
+    TRY(gemm_axis<T>(p, ax, a.P, tmp));
+    StageArgs<T> b = a;
+    b.P = tmp;
+    hipLaunchKernelGGL((k_zadj<T, NoXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[ax], p->stream, b);
+    HIPCHECK(hipGetLastError());
+    TRY(gemm_axis<T>(p, ax, tmp, a.P));
   } else
     hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
                        p->lds[ax], p->stream, a);
@@ -1071,13 +1172,14 @@ void destroy_plan(sfrde_plan_s* p) {
   void** ptrs[] = {&p->Mt[0], &p->Mt[1], &p->Mt[2], (void**)&p->lam[0], (void**)&p->lam[1],
                    (void**)&p->lam[2], &p->coef, &p->dcoef, &p->ltab, &p->P, &p->uhat, &p->ctil, &p->acc,
                    &p->Pa, &p->zh, &p->aacc, &p->ahat, &p->gu, (void**)&p->G, &p->seg,
-                   (void**)&p->rp_acc, (void**)&p->thp, (void**)&p->red, (void**)&p->flag, (void**)&p->rxm, &p->mf_A[0],
+                   (void**)&p->rp_acc, (void**)&p->thp, (void**)&p->red, (void**)&p->flag, (void**)&p->rxm, &p->gtmp, &p->mf_A[0],
                    &p->mf_A[1], &p->mf_A[2]};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
   if (p->h_flag) (void)hipHostFree(p->h_flag);
+  if (p->blas) (void)rocblas_destroy_handle(p->blas);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   delete p;
 }
@@ -1157,6 +1259,25 @@ int build_plan(sfrde_plan_s* p) {
   for (int a = 0; a < p->ndim; ++a)
     make_geom(p, a, std::max<long long>(1, (2LL * p->n_cu + p->B - 1) / p->B));
   for (int a = 0; a < p->ndim; ++a) TRY(setup_mfma_axis(p, a));
+  {
+    // Axes the matrix-core engine does not take (periodic n >= 256, others
+    // n > 256): library matrix products (SFRDE_TRANSFORM=dense keeps the
+    // LDS kernels). The one-point padding axis of 1D plans stays dense.
+    const char* env = getenv("SFRDE_TRANSFORM");
+    const bool dense_only = env && strcmp(env, "dense") == 0;
+    bool any = false;
+    for (int a = 0; a < p->ndim; ++a) {
+      p->use_g[a] = !dense_only && !p->use_m[a] && p->n[a] >= 64;
+      any = any || p->use_g[a];
+    }
+    if (any) {
+      if (rocblas_create_handle(&p->blas) != rocblas_status_success)
+        return fail(SFRDE_EDEVICE, "rocblas_create_handle failed");
+      if (rocblas_set_stream(p->blas, p->stream) != rocblas_status_success)
+        return fail(SFRDE_EDEVICE, "rocblas_set_stream failed");
+      TRY(dev_alloc(p, &p->gtmp, field_bytes(p)));
+    }
+  }
   {
     // FP32 P13 plans whose last axis runs the vector Z kernels form L there
     // from the eigenvalue tables (kept in LDS as floats) instead of reading

@@ -8,7 +8,7 @@ import workloads as W
 from oracle import problem
 from paper_2003_13569_amd.torch_api import SFRDEFunction
 from tests.gpu_util import TD, plan_for
-from tests.test_gpu_parity import CASES, VEC_CASES
+from tests.test_gpu_parity import CASES, DENSE_CASES, VEC_CASES
 
 pytestmark = pytest.mark.gpu
 
@@ -125,3 +125,16 @@ def test_incompatible_checkpoint_is_rejected():
         p.backward(ckpt, 6, 2, torch.zeros_like(u))
     assert ei.value.code == C.ESTATE
     p.close()
+
+
+@pytest.mark.parametrize("wl", DENSE_CASES, ids=[c.name for c in DENSE_CASES])
+def test_fp64_adjoint_library_product_axes_match_oracle(wl):
+    # axes past the matrix-core engine (library matrix products)
+    u0 = W.initial_fields(wl)
+    wbar = np.random.default_rng(13).standard_normal(u0.shape)
+    ref = problem.gradients(wl, u0, M, wbar)
+    got = _gpu_grads(wl, u0, wbar, "f64")
+    assert _rel(got["u0"], ref["u0"]) <= 1e-9
+    for key in ("kappa", "alpha", "params"):
+        r, g = ref[key], got[key]
+        assert np.max(np.abs(g - r)) <= 1e-9 * max(np.max(np.abs(r)), 1e-300), (key, g, r)

@@ -11,7 +11,7 @@ import workloads as W
 from oracle import problem
 from paper_2003_13569_amd.torch_api import Plan
 from tests.gpu_util import TD
-from tests.test_gpu_parity import CASES, VEC_CASES
+from tests.test_gpu_parity import CASES, DENSE_CASES, VEC_CASES
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def _batch_plan(members, dtype):
                 batch=len(members))
 
 
-BATCH_CASES = [CASES[2], CASES[3], CASES[6]]   # gm2d-neu, sch2d-dir, gs3d-per
+BATCH_CASES = [CASES[2], CASES[3], CASES[6], DENSE_CASES[1]]  # ..., a library-product axis
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])

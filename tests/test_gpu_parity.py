@@ -108,6 +108,29 @@ def test_dense_axes_match_oracle(wl, dtype, tol):
     assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
 
 
+def test_lds_dense_kernels_match_oracle(monkeypatch):
+    # SFRDE_TRANSFORM=dense: the long axes take the LDS dense kernels instead of
+    # library matrix products.
+    monkeypatch.setenv("SFRDE_TRANSFORM", "dense")
+    for wl in DENSE_CASES:
+        u0 = W.initial_fields(wl)
+        ref = problem.run(wl, u0, 3)
+        assert problem.rel_err(run(wl, u0, 3, "f64"), ref) <= 1e-10
+        assert problem.rel_err(run(wl, u0, 3, "f32"), ref) <= 2e-5
+
+
+# The benchmark configurations at their full sizes, a few steps.
+FULL = [W.C2_GS, W.C3_SCHNAK_DIR, W.C4_GM_ADJ]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+@pytest.mark.parametrize("wl", FULL, ids=[c.name for c in FULL])
+def test_configs_full_size_match_oracle(wl, dtype, tol):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 3)
+    assert problem.rel_err(run(wl, u0, 3, dtype), ref) <= tol
+
+
 # The paper's own applications (Section 5.2) at its grids, constants and
 # deterministic initial data; GM with different orders per species.
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
