@@ -132,6 +132,32 @@ def summarize_stats(stats_csv):
               f"{tot / 1e6:.3f} | {pct:.1f} % |")
 
 
+def time_configs(W, Plan, torch, time):
+    """The remaining benchmark configurations at their full sizes (context for
+    the headline; each is also a parity test case): ms per step."""
+    configs = {}
+    for c, dt_c, kc in ((W.C1_FHN, "f64", 200), (W.C2_GS, "f32", 100), (W.C2_GS, "f64", 50),
+                        (W.C3_SCHNAK_DIR, "f32", 50), (W.C3_SCHNAK_DIR, "f64", 20),
+                        (W.C4_GM_ADJ, "f32", 100)):
+        pc = Plan(c.shape, c.bc, c.h, c.alpha, c.kappa, c.dt, c.reaction, c.params, dt_c,
+                  c.scheme)
+        uc = torch.tensor(W.initial_fields(c), dtype=torch.float32 if dt_c == "f32"
+                          else torch.float64, device="cuda")
+        pc.integrate(uc.clone(), 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pc.integrate(uc, kc)
+        torch.cuda.synchronize()
+        msc = (time.perf_counter() - t0) * 1e3 / kc
+        configs[f"{c.name}_{dt_c}"] = {
+            "ms_per_step": round(msc, 4), "steps": kc,
+            "Mpoint_steps_per_s": round(c.npoints / (msc * 1e-3) / 1e6, 1)}
+        print(f"[bench] {c.name} {dt_c}: {msc:.4f} ms/step", flush=True)
+        pc.close()
+        del uc
+    return configs
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +171,10 @@ def main() -> int:
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the timings of the other benchmark configurations")
+    ap.add_argument("--configs-only", action="store_true",
+                    help="time only the other configurations (one JSON line)")
     ap.add_argument("--ensemble-members", type=int, default=64)
     ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -191,6 +221,10 @@ def main() -> int:
     from paper_2003_13569_amd.torch_api import Plan
 
     C.lib()  # fails loudly if the HIP library is missing
+
+    if args.configs_only:
+        print(json.dumps({"configs": time_configs(W, Plan, torch, time)}), flush=True)
+        return 0
 
     wl = W.C5_SCHNAK_NEU.replace(alpha=(args.alpha, args.alpha))
     S, n = wl.nspecies, wl.npoints
@@ -346,6 +380,9 @@ def main() -> int:
         single.close()
         batch.close()
 
+    # ---------------------------------------------------------------- other configs
+    configs = None if args.no_configs else time_configs(W, Plan, torch, time)
+
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
@@ -387,6 +424,7 @@ def main() -> int:
         "error": {"fp32_vs_fp64_gpu": err, "steps": args.fp64_steps} if err is not None else None,
         "adjoint": adjoint,
         "ensemble": ensemble,
+        "configs": configs,
         "roofline": roofline,
         "step_effective_gbs": round(step_gbs, 1),
         "kernels": kernels,
