@@ -647,6 +647,7 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
   } else if (p->use_g[axis]) {
     // library product through gtmp; the weights (or a copy) in a pointwise pass
     T* tmp = (T*)p->gtmp;
+    a.g = p->geom[0];  // pointwise only: contiguous x-line tiles
     const dim3 grid((unsigned)a.g.ntiles, p->B);
     if (!a.pre_divide_w && !a.post_multiply_w && src != dst) {
       TRY(gemm_axis<T>(p, axis, (const T*)src, (T*)dst));
@@ -654,14 +655,14 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
       SingleArgs<T> w = a;
       w.dst = tmp;
       w.post_multiply_w = 0;
-      hipLaunchKernelGGL((k_single<T, NoXf>), grid, dim3(NTHREADS), p->lds[axis], p->stream, w);
+      hipLaunchKernelGGL((k_single<T, NoXf>), grid, dim3(NTHREADS), p->lds[0], p->stream, w);
       HIPCHECK(hipGetLastError());
       TRY(gemm_axis<T>(p, axis, tmp, (T*)dst));
     } else {
       TRY(gemm_axis<T>(p, axis, (const T*)src, tmp));
       SingleArgs<T> w = a;
       w.src = tmp;
-      hipLaunchKernelGGL((k_single<T, NoXf>), grid, dim3(NTHREADS), p->lds[axis], p->stream, w);
+      hipLaunchKernelGGL((k_single<T, NoXf>), grid, dim3(NTHREADS), p->lds[0], p->stream, w);
     }
   } else
     hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
@@ -768,8 +769,9 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat)
     if (!src) TRY(gemm_axis<T>(p, ax, a.P, tmp));
     StageArgs<T> b = a;
     b.P = tmp;
-    hipLaunchKernelGGL((k_zstage<T, NoXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
-                       p->lds[ax], p->stream, b);
+    b.g = p->geom[0];  // pointwise only: contiguous x-line tiles
+    hipLaunchKernelGGL((k_zstage<T, NoXf>), dim3((unsigned)b.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[0], p->stream, b);
     HIPCHECK(hipGetLastError());
     TRY(gemm_axis<T>(p, ax, tmp, a.P));
   } else
@@ -966,8 +968,9 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
     TRY(gemm_axis<T>(p, ax, a.P, tmp));
     StageArgs<T> b = a;
     b.P = tmp;
-    hipLaunchKernelGGL((k_zadj<T, NoXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
-                       p->lds[ax], p->stream, b);
+    b.g = p->geom[0];  // pointwise only: contiguous x-line tiles
+    hipLaunchKernelGGL((k_zadj<T, NoXf>), dim3((unsigned)b.g.ntiles, p->B), dim3(NTHREADS),
+                       p->lds[0], p->stream, b);
     HIPCHECK(hipGetLastError());
     TRY(gemm_axis<T>(p, ax, tmp, a.P));
   } else
