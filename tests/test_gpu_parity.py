@@ -141,6 +141,54 @@ def test_paper_applications_match_oracle(wl, dtype, tol):
     assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
 
 
+_C5_REF = {}
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+def test_config5_full_size_one_step_matches_oracle(dtype, tol):
+    # 3D Schnakenberg Neumann 256^3 (the benchmark workload), one step; the
+    # oracle's step takes seconds on the host cores.
+    wl = W.C5_SCHNAK_NEU
+    u0 = W.initial_fields(wl)
+    if "ref" not in _C5_REF:
+        _C5_REF["ref"] = problem.run(wl, u0, 1)
+    assert problem.rel_err(run(wl, u0, 1, dtype), _C5_REF["ref"]) <= tol
+
+
+@pytest.mark.parametrize("wl,alpha", [(W.C3_SCHNAK_DIR, 1.8), (W.C5_SCHNAK_NEU, 1.2),
+                                      (W.C5_SCHNAK_NEU, 1.9)],
+                         ids=["c3-500", "c5-a1.2-1000", "c5-a1.9-1000"])
+def test_fp32_full_horizon_matches_fp64_gpu(wl, alpha):
+    # FP32 against the FP64 GPU path (itself pinned to the oracle above) over
+    # the configuration's whole horizon.
+    wl = wl.replace(alpha=(alpha, alpha))
+    u0 = W.initial_fields(wl)
+    a = run(wl, u0, wl.nsteps, "f32")
+    b = run(wl, u0, wl.nsteps, "f64")
+    assert problem.rel_err(a, b) <= 2e-5
+
+
+# The largest axes a plan accepts (1024 unknowns), on each kind of axis:
+# contiguous x, strided middle and strided last (library products), ragged
+# partners on the other axes.
+MAX_CASES = [
+    _wl("max2d-neu", "neumann", (1024, 700), "gray_scott", GS, (1.7, 1.5), (2e-3, 1e-3), 0.5,
+        "gs_square", (-1.0, 1.0)),
+    _wl("max3d-dir-z", "dirichlet", (1024, 6, 5), "schnakenberg", SCH, (1.8, 1.6), (0.05, 1.0),
+        0.01, "schnak_noise", (0.0, 1.0)),
+    _wl("max3d-per-x", "periodic", (5, 6, 1024), "schnakenberg", SCH, (1.8, 1.6), (0.05, 1.0),
+        0.01, "schnak_noise", (0.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+@pytest.mark.parametrize("wl", MAX_CASES, ids=[c.name for c in MAX_CASES])
+def test_largest_axes_match_oracle(wl, dtype, tol):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 2)
+    assert problem.rel_err(run(wl, u0, 2, dtype), ref) <= tol
+
+
 def test_linear_reaction_many_species():
     wl = W.Workload(name="lin4", bc="dirichlet", shape=(14, 19), domain=(0.0, 1.0),
                     alpha=(1.2, 1.5, 1.8, 2.0), kappa=(0.01, 0.02, 0.0, 0.05),
