@@ -21,9 +21,13 @@
  *
  * Conventions for every entry point
  * ---------------------------------
- * - Fields are device arrays [S][nz][ny][nx] (2D: [S][ny][nx]) of the plan's
- *   dtype, x contiguous. Sizes are *unknowns* per axis: N = n (periodic),
- *   n + 1 (Dirichlet), n - 1 (Neumann) intervals with spacing h per axis.
+ * - Fields are device arrays [S][nz][ny][nx] (2D: [S][ny][nx], 1D: [S][nx])
+ *   of the plan's dtype, x contiguous; ensemble plans (sfrde_plan_batch) put
+ *   the member first, [B][S][...]. Sizes are *unknowns* per axis: N = n
+ *   (periodic), n + 1 (Dirichlet), n - 1 (Neumann) intervals with spacing h.
+ * - Axes of up to 256 points (255 periodic) run on hand-written matrix-core
+ *   kernels; longer axes (up to 1024) run their transforms as rocBLAS matrix
+ *   products around the same pointwise kernels.
  * - n[0] is the x (fastest) extent, n[1] y, n[2] z; h[] in the same order.
  * - The caller owns every buffer passed in (state, checkpoints, gradients)
  *   and the stream; the library never frees caller memory. The plan owns its
