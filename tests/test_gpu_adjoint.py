@@ -138,3 +138,76 @@ def test_fp64_adjoint_library_product_axes_match_oracle(wl):
     for key in ("kappa", "alpha", "params"):
         r, g = ref[key], got[key]
         assert np.max(np.abs(g - r)) <= 1e-9 * max(np.max(np.abs(r)), 1e-300), (key, g, r)
+
+
+def _c4_loss_and_grads(dtype, kappa, alpha, params, u0, target, with_grads):
+    """Config 4 (Gierer-Meinhardt 256^2 Neumann, 200 steps of dt = 0.05):
+    loss = mean over points of sum over species of (u_T - u*)^2."""
+    wl = W.C4_GM_ADJ
+    p = plan_for(wl, dtype, alpha=alpha, kappa=kappa, params=params)
+    u = torch.tensor(u0, dtype=TD[dtype], device="cuda")
+    npts = wl.npoints
+    if not with_grads:
+        p.integrate(u, wl.nsteps)
+        d = u.double() - target
+        loss = float((d * d).sum()) / npts
+        p.close()
+        return loss
+    ck = p.integrate(u, wl.nsteps, 0.0, ckpt_every=wl.ckpt_every)
+    d = u.double() - target
+    loss = float((d * d).sum()) / npts
+    g_uT = (2.0 / npts * d).to(TD[dtype]).contiguous()
+    g_u0 = torch.empty_like(g_uT)
+    gk, ga, gp = p.backward(ck, wl.nsteps, wl.ckpt_every, g_uT, 0.0, g_u0)
+    torch.cuda.synchronize()
+    p.close()
+    return loss, g_u0.double(), np.array(gk), np.array(ga), np.array(gp)
+
+
+def test_config4_adjoint_full_size_matches_central_differences():
+    # Config 4 as specified: MSE after 200 steps against a target run with
+    # perturbed parameters, gradients of u0, kappa, alpha and the reaction
+    # constants with checkpoints every 20 steps, against central differences
+    # in FP64 (steps of 1e-4 relative, at least 1e-6); the FP32 adjoint against
+    # the FP64 one.
+    wl = W.C4_GM_ADJ
+    tg = wl.extra["target"]
+    u0 = W.initial_fields(wl)
+    pt = plan_for(wl, "f64", alpha=tg["alpha"], kappa=tg["kappa"], params=tg["params"])
+    target = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    pt.integrate(target, wl.nsteps)
+    pt.close()
+    kap, alp, par = list(wl.kappa), list(wl.alpha), list(wl.params)
+    loss, gu0, gk, ga, gp = _c4_loss_and_grads("f64", kap, alp, par, u0, target, True)
+    assert loss > 0
+
+    def fd(which, i):
+        vals = {"kappa": kap, "alpha": alp, "params": par}
+        out = []
+        for sgn in (1.0, -1.0):
+            v = {k: list(x) for k, x in vals.items()}
+            step = 1e-4 * max(abs(v[which][i]), 1e-2)
+            v[which][i] += sgn * step
+            out.append(_c4_loss_and_grads("f64", v["kappa"], v["alpha"], v["params"], u0,
+                                          target, False))
+        return (out[0] - out[1]) / (2 * step)
+
+    for which, g in (("kappa", gk), ("alpha", ga), ("params", gp)):
+        for i in range(len(g)):
+            ref = fd(which, i)
+            assert abs(g[i] - ref) <= 1e-4 * abs(ref), (which, i, g[i], ref)
+    # u0 along a random direction
+    v = torch.tensor(np.random.default_rng(17).standard_normal(u0.shape), device="cuda")
+    eps = 1e-4
+    lp = _c4_loss_and_grads("f64", kap, alp, par, (torch.tensor(u0, device="cuda") + eps * v)
+                            .cpu().numpy(), target, False)
+    lm = _c4_loss_and_grads("f64", kap, alp, par, (torch.tensor(u0, device="cuda") - eps * v)
+                            .cpu().numpy(), target, False)
+    fdu = (lp - lm) / (2 * eps)
+    ad = float((gu0 * v).sum())
+    assert abs(ad - fdu) <= 1e-4 * abs(fdu), (ad, fdu)
+    # the FP32 path (the configuration's precision) against the FP64 adjoint
+    _, gu0_32, gk32, ga32, gp32 = _c4_loss_and_grads("f32", kap, alp, par, u0, target, True)
+    assert _rel(gu0_32.cpu().numpy(), gu0.cpu().numpy()) <= 1e-3
+    for a, b in ((gk32, gk), (ga32, ga), (gp32, gp)):
+        assert np.max(np.abs(a - b)) <= 1e-3 * np.max(np.abs(b)), (a, b)
