@@ -709,6 +709,53 @@ __device__ __forceinline__ void xadj_reaction_vec(const StageArgs<float>& a, flo
   }
 }
 
+// Forward reaction on an x tile in the XTileIO layout: each thread takes 4
+// consecutive points of a line (all species) per vector, with every LDS read
+// of a vector issued before its arithmetic (conflict-free, as the tile
+// commit). The same per-point arithmetic as pw_reaction_n; the stage values
+// are stored for the adjoint by the caller.
+template <int NS>
+__device__ __forceinline__ bool x_reaction_vec(const StageArgs<float>& a, float* buf) {
+  using IO = XTileIO<32>;
+  const Geom& g = a.g;
+  const RxnT<float> rx(a.rxn);
+  const int n = g.n;
+  const int nv = 1 << IO::vshift(g);  // vectors per species, a multiple of 512
+  bool bad = false;
+#pragma unroll 1
+  for (int q = threadIdx.x; q < nv; q += 512) {
+    int go, lo;
+    IO::coords(g, 0, q, go, lo);
+    float u[4][NS];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int s = 0; s < NS; ++s) u[e][s] = buf[lo + s * n * IO::P + e * IO::P];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float f[NS];
+      rxn_eval_t<float, NS>(rx, u[e], f);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        bad |= !isfinite(u[e][s]) || !isfinite(f[s]);
+        buf[lo + s * n * IO::P + e * IO::P] = f[s];
+      }
+    }
+  }
+  return bad;
+}
+
+// Forward reaction of the FAST x kernels: the vector path for one or two
+// species without a manufactured source, else the generic pass.
+__device__ __forceinline__ bool x_reaction_fast(const StageArgs<float>& a, float* buf,
+                                                long long tile) {
+  if (a.rxn.kind < RXN_HUXLEY_MMS) {
+    if (a.S == 2) return x_reaction_vec<2>(a, buf);
+    if (a.S == 1) return x_reaction_vec<1>(a, buf);
+  }
+  return pw_reaction(a, buf, tile, false);
+}
+
 __device__ __forceinline__ void xadj_reaction_fast(const StageArgs<float>& a, float* buf,
                                                    long long tile, double* pacc) {
   switch (a.S) {
@@ -1276,7 +1323,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
                                 a.st_phys + (long long)a.mode * S * a.g.total);
           __syncthreads();
         }
-        bad |= pw_reaction(a, buf, tile, false);
+        bad |= x_reaction_fast(a, buf, tile);
         __syncthreads();
         xf(buf, S);
         tile_store<T, XF::W, FAST, true>(a.g, tile, buf, a.P);
@@ -1301,7 +1348,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
                               a.st_phys + (long long)a.mode * S * a.g.total);
         __syncthreads();
       }
-      bad |= pw_reaction(a, buf, tile, false);
+      bad |= x_reaction_fast(a, buf, tile);
     } else {
       bad |= pw_reaction(a, buf, tile);
     }
