@@ -714,7 +714,7 @@ __device__ __forceinline__ void xadj_reaction_vec(const StageArgs<float>& a, flo
 // of a vector issued before its arithmetic (conflict-free, as the tile
 // commit). The same per-point arithmetic as pw_reaction_n; the stage values
 // are stored for the adjoint by the caller.
-template <int NS>
+template <int NS, int KIND>
 __device__ __forceinline__ bool x_reaction_vec(const StageArgs<float>& a, float* buf) {
   using IO = XTileIO<32>;
   const Geom& g = a.g;
@@ -734,7 +734,7 @@ __device__ __forceinline__ bool x_reaction_vec(const StageArgs<float>& a, float*
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       float f[NS];
-      rxn_eval_t<float, NS>(rx, u[e], f);
+      rxn_eval_k<float, NS, KIND>(rx, u[e], f);
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         bad |= !isfinite(u[e][s]) || !isfinite(f[s]);
@@ -749,10 +749,18 @@ __device__ __forceinline__ bool x_reaction_vec(const StageArgs<float>& a, float*
 // species without a manufactured source, else the generic pass.
 __device__ __forceinline__ bool x_reaction_fast(const StageArgs<float>& a, float* buf,
                                                 long long tile) {
-  if (a.rxn.kind < RXN_HUXLEY_MMS) {
-    if (a.S == 2) return x_reaction_vec<2>(a, buf);
-    if (a.S == 1) return x_reaction_vec<1>(a, buf);
+  // the kind is uniform: one loop per kind, no branch inside it
+  if (a.S == 2) {
+    switch (a.rxn.kind) {
+      case RXN_LINEAR: return x_reaction_vec<2, RXN_LINEAR>(a, buf);
+      case RXN_FHN: return x_reaction_vec<2, RXN_FHN>(a, buf);
+      case RXN_GRAY_SCOTT: return x_reaction_vec<2, RXN_GRAY_SCOTT>(a, buf);
+      case RXN_SCHNAKENBERG: return x_reaction_vec<2, RXN_SCHNAKENBERG>(a, buf);
+      case RXN_GM: return x_reaction_vec<2, RXN_GM>(a, buf);
+      default: break;
+    }
   }
+  if (a.S == 1 && a.rxn.kind == RXN_LINEAR) return x_reaction_vec<1, RXN_LINEAR>(a, buf);
   return pw_reaction(a, buf, tile, false);
 }
 

@@ -41,47 +41,65 @@ struct RxnT {
   }
 };
 
+// f = f(u) for a reaction kind fixed at compile time (KIND), NS species.
+template <typename T, int NS, int KIND>
+__device__ __forceinline__ void rxn_eval_k(const RxnT<T>& r, const T* u, T* f) {
+  if constexpr (KIND == RXN_LINEAR) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s) f[s] = r.lin[s] * u[s];
+  } else if constexpr (NS == 1) {
+    // the pointwise parts of Examples 1 and 2 (the source is added by the
+    // caller, which knows the point and the stage time)
+    const T x = u[0];
+    if constexpr (KIND == RXN_HUXLEY_MMS)
+      f[0] = x * (T(1) - x) * (x - T(1));
+    else
+      f[0] = x - x * x;
+  } else if constexpr (NS == 2) {
+    const T x = u[0], v = u[1];
+    if constexpr (KIND == RXN_FHN) {
+      f[0] = x * (T(1) - x) * (x - r.p[0]) - v;
+      f[1] = r.p[1] * (r.p[2] * x - r.p[3] * v - r.p[4]);
+    } else if constexpr (KIND == RXN_GRAY_SCOTT) {
+      const T xvv = x * v * v;
+      f[0] = -xvv + r.p[0] * (T(1) - x);
+      f[1] = xvv - (r.p[0] + r.p[1]) * v;
+    } else if constexpr (KIND == RXN_SCHNAKENBERG) {
+      const T xxv = x * x * v;
+      f[0] = r.p[0] * (r.p[1] - x + xxv);
+      f[1] = r.p[0] * (r.p[2] - xxv);
+    } else {  // Gierer-Meinhardt
+      f[0] = r.p[0] - r.p[1] * x + r.p[2] * x * x / v;
+      f[1] = r.p[3] * x * x - r.p[4] * v;
+    }
+  }
+}
+
 // NS = number of species, fixed at compile time so that the per-point
-// arrays stay in registers.
+// arrays stay in registers; the kind is taken at run time.
 template <typename T, int NS>
 __device__ __forceinline__ void rxn_eval_t(const RxnT<T>& r, const T* u, T* f) {
   switch (r.kind) {
     case RXN_LINEAR:
-#pragma unroll
-      for (int s = 0; s < NS; ++s) f[s] = r.lin[s] * u[s];
+      rxn_eval_k<T, NS, RXN_LINEAR>(r, u, f);
+      break;
+    case RXN_FHN:
+      rxn_eval_k<T, NS, RXN_FHN>(r, u, f);
+      break;
+    case RXN_GRAY_SCOTT:
+      rxn_eval_k<T, NS, RXN_GRAY_SCOTT>(r, u, f);
+      break;
+    case RXN_SCHNAKENBERG:
+      rxn_eval_k<T, NS, RXN_SCHNAKENBERG>(r, u, f);
+      break;
+    case RXN_GM:
+      rxn_eval_k<T, NS, RXN_GM>(r, u, f);
+      break;
+    case RXN_HUXLEY_MMS:
+      rxn_eval_k<T, NS, RXN_HUXLEY_MMS>(r, u, f);
       break;
     default:
-      if constexpr (NS == 1) {
-        // the pointwise parts of Examples 1 and 2 (the source is added by
-        // the caller, which knows the point and the stage time)
-        const T x = u[0];
-        f[0] = r.kind == RXN_HUXLEY_MMS ? x * (T(1) - x) * (x - T(1)) : x - x * x;
-      }
-      if constexpr (NS == 2) {
-        const T x = u[0], v = u[1];
-        switch (r.kind) {
-          case RXN_FHN:
-            f[0] = x * (T(1) - x) * (x - r.p[0]) - v;
-            f[1] = r.p[1] * (r.p[2] * x - r.p[3] * v - r.p[4]);
-            break;
-          case RXN_GRAY_SCOTT: {
-            const T xvv = x * v * v;
-            f[0] = -xvv + r.p[0] * (T(1) - x);
-            f[1] = xvv - (r.p[0] + r.p[1]) * v;
-            break;
-          }
-          case RXN_SCHNAKENBERG: {
-            const T xxv = x * x * v;
-            f[0] = r.p[0] * (r.p[1] - x + xxv);
-            f[1] = r.p[0] * (r.p[2] - xxv);
-            break;
-          }
-          default:  // Gierer-Meinhardt
-            f[0] = r.p[0] - r.p[1] * x + r.p[2] * x * x / v;
-            f[1] = r.p[3] * x * x - r.p[4] * v;
-            break;
-        }
-      }
+      rxn_eval_k<T, NS, RXN_FISHER_MMS>(r, u, f);
       break;
   }
 }
