@@ -441,7 +441,7 @@ __device__ __forceinline__ double mms_source(const Rxn& r, double t, long long i
 // Forward reaction: buf holds the stage value (physical); replaced by f.
 // Walks the LDS tile row by row (lanes w fastest); the global index is only
 // formed when stage values are stored.
-template <typename T, int NS>
+template <typename T, int NS, int KIND>
 __device__ __forceinline__ bool pw_reaction_n(const StageArgs<T>& a, T* buf, long long tile,
                                               bool record) {
   const Geom& g = a.g;
@@ -462,12 +462,10 @@ __device__ __forceinline__ bool pw_reaction_n(const StageArgs<T>& a, T* buf, lon
 #pragma unroll
       for (int s = 0; s < NS; ++s) a.st_phys[((long long)a.mode * NS + s) * g.total + idx] = u[s];
     }
-    rxn_eval_t<T, NS>(rx, u, f);
-    if constexpr (NS == 1) {
-      if (rx.kind >= RXN_HUXLEY_MMS) {
-        const long long idx = tr.base + (long long)j * tr.rs + (long long)w * tr.cs;
-        f[0] += T(mms_source(a.rxn, a.t, idx, a.n0, a.n1));
-      }
+    rxn_eval_k<T, NS, KIND>(rx, u, f);
+    if constexpr (NS == 1 && KIND >= RXN_HUXLEY_MMS) {
+      const long long idx = tr.base + (long long)j * tr.rs + (long long)w * tr.cs;
+      f[0] += T(mms_source(a.rxn, a.t, idx, a.n0, a.n1));
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -483,15 +481,26 @@ template <typename T>
 __device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long long tile,
                                             bool record = true) {
   record = record && a.st_phys != nullptr;
+  // the kind is uniform: one loop per (species count, kind), no branch inside
   switch (a.S) {
     case 1:
-      return pw_reaction_n<T, 1>(a, buf, tile, record);
+      switch (a.rxn.kind) {
+        case RXN_LINEAR: return pw_reaction_n<T, 1, RXN_LINEAR>(a, buf, tile, record);
+        case RXN_HUXLEY_MMS: return pw_reaction_n<T, 1, RXN_HUXLEY_MMS>(a, buf, tile, record);
+        default: return pw_reaction_n<T, 1, RXN_FISHER_MMS>(a, buf, tile, record);
+      }
     case 2:
-      return pw_reaction_n<T, 2>(a, buf, tile, record);
+      switch (a.rxn.kind) {
+        case RXN_LINEAR: return pw_reaction_n<T, 2, RXN_LINEAR>(a, buf, tile, record);
+        case RXN_FHN: return pw_reaction_n<T, 2, RXN_FHN>(a, buf, tile, record);
+        case RXN_GRAY_SCOTT: return pw_reaction_n<T, 2, RXN_GRAY_SCOTT>(a, buf, tile, record);
+        case RXN_SCHNAKENBERG: return pw_reaction_n<T, 2, RXN_SCHNAKENBERG>(a, buf, tile, record);
+        default: return pw_reaction_n<T, 2, RXN_GM>(a, buf, tile, record);
+      }
     case 3:
-      return pw_reaction_n<T, 3>(a, buf, tile, record);
+      return pw_reaction_n<T, 3, RXN_LINEAR>(a, buf, tile, record);
     default:
-      return pw_reaction_n<T, 4>(a, buf, tile, record);
+      return pw_reaction_n<T, 4, RXN_LINEAR>(a, buf, tile, record);
   }
 }
 
@@ -737,7 +746,7 @@ __device__ __forceinline__ void pw_combine_fast(const StageArgs<T>& a, T* buf, l
 // Adjoint reaction: buf holds the cotangent of f(stage value) (physical);
 // replaced by J^T of it at the stored stage value. Reaction-parameter
 // partials are added to pacc (weighted by the Neumann point weights).
-template <typename T, int NS>
+template <typename T, int NS, int KIND>
 __device__ __forceinline__ void pw_adj_reaction_n(const StageArgs<T>& a, T* buf, long long tile,
                                                   double* pacc) {
   const Geom& g = a.g;
@@ -756,7 +765,7 @@ __device__ __forceinline__ void pw_adj_reaction_n(const StageArgs<T>& a, T* buf,
       u[s] = a.st_phys[((long long)a.mode * NS + s) * g.total + idx];
     }
     const double wgt = a.neumann ? point_weight(idx, a.n0, a.n1, a.n2) : 1.0;
-    rxn_adjoint<T, NS>(a.rxn, u, gg, o, wgt, pacc, want_p);
+    rxn_adjoint_k<T, NS, KIND>(a.rxn, u, gg, o, wgt, pacc, want_p);
 #pragma unroll
     for (int s = 0; s < NS; ++s) buf[(s * g.n + j) * g.pitch + w] = o[s];
   }
@@ -765,18 +774,29 @@ __device__ __forceinline__ void pw_adj_reaction_n(const StageArgs<T>& a, T* buf,
 template <typename T>
 __device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, long long tile,
                                                 double* pacc) {
+  // the kind is uniform: one loop per (species count, kind)
   switch (a.S) {
     case 1:
-      pw_adj_reaction_n<T, 1>(a, buf, tile, pacc);
+      switch (a.rxn.kind) {
+        case RXN_LINEAR: pw_adj_reaction_n<T, 1, RXN_LINEAR>(a, buf, tile, pacc); break;
+        case RXN_HUXLEY_MMS: pw_adj_reaction_n<T, 1, RXN_HUXLEY_MMS>(a, buf, tile, pacc); break;
+        default: pw_adj_reaction_n<T, 1, RXN_FISHER_MMS>(a, buf, tile, pacc); break;
+      }
       break;
     case 2:
-      pw_adj_reaction_n<T, 2>(a, buf, tile, pacc);
+      switch (a.rxn.kind) {
+        case RXN_LINEAR: pw_adj_reaction_n<T, 2, RXN_LINEAR>(a, buf, tile, pacc); break;
+        case RXN_FHN: pw_adj_reaction_n<T, 2, RXN_FHN>(a, buf, tile, pacc); break;
+        case RXN_GRAY_SCOTT: pw_adj_reaction_n<T, 2, RXN_GRAY_SCOTT>(a, buf, tile, pacc); break;
+        case RXN_SCHNAKENBERG: pw_adj_reaction_n<T, 2, RXN_SCHNAKENBERG>(a, buf, tile, pacc); break;
+        default: pw_adj_reaction_n<T, 2, RXN_GM>(a, buf, tile, pacc); break;
+      }
       break;
     case 3:
-      pw_adj_reaction_n<T, 3>(a, buf, tile, pacc);
+      pw_adj_reaction_n<T, 3, RXN_LINEAR>(a, buf, tile, pacc);
       break;
     default:
-      pw_adj_reaction_n<T, 4>(a, buf, tile, pacc);
+      pw_adj_reaction_n<T, 4, RXN_LINEAR>(a, buf, tile, pacc);
       break;
   }
 }

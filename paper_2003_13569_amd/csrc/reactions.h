@@ -105,29 +105,27 @@ __device__ __forceinline__ void rxn_eval_t(const RxnT<T>& r, const T* u, T* f) {
 }
 
 // out = J_f(u)^T g (out_r = sum_s g_s d f_s / d u_r), and
-// pacc[k] += wgt * sum_s g_s d f_s / d p_k.
-template <typename T, int NS>
-__device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g, T* out,
-                                            double wgt, double* pacc, bool want_p) {
-  if (r.kind == RXN_LINEAR) {
+// pacc[k] += wgt * sum_s g_s d f_s / d p_k, for a kind fixed at compile time.
+template <typename T, int NS, int KIND>
+__device__ __forceinline__ void rxn_adjoint_k(const Rxn& r, const T* u, const T* g, T* out,
+                                              double wgt, double* pacc, bool want_p) {
+  if constexpr (KIND == RXN_LINEAR) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       out[s] = T(r.p[s]) * g[s];
       if (want_p) pacc[s] += wgt * double(g[s] * u[s]);
     }
-    return;
-  }
-  if constexpr (NS == 1) {
+  } else if constexpr (NS == 1) {
     // Examples 1 and 2: the sources do not depend on u
     const T x = u[0];
-    out[0] = r.kind == RXN_HUXLEY_MMS ? -g[0] * (x - T(1)) * (T(3) * x - T(1))
-                                      : g[0] * (T(1) - T(2) * x);
-  }
-  if constexpr (NS == 2) {
-  switch (r.kind) {
-    case RXN_FHN: {
+    if constexpr (KIND == RXN_HUXLEY_MMS)
+      out[0] = -g[0] * (x - T(1)) * (T(3) * x - T(1));
+    else
+      out[0] = g[0] * (T(1) - T(2) * x);
+  } else if constexpr (NS == 2) {
+    const T x = u[0], v = u[1], gu = g[0], gv = g[1];
+    if constexpr (KIND == RXN_FHN) {
       const T mu = T(r.p[0]), eps = T(r.p[1]), beta = T(r.p[2]), gam = T(r.p[3]), dlt = T(r.p[4]);
-      const T x = u[0], v = u[1], gu = g[0], gv = g[1];
       const T dfu_du = -T(3) * x * x + T(2) * (T(1) + mu) * x - mu;
       out[0] = gu * dfu_du + gv * eps * beta;
       out[1] = -gu - gv * eps * gam;
@@ -138,11 +136,8 @@ __device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g
         pacc[3] += wgt * double(-gv * eps * v);
         pacc[4] += wgt * double(-gv * eps);
       }
-      break;
-    }
-    case RXN_GRAY_SCOTT: {
+    } else if constexpr (KIND == RXN_GRAY_SCOTT) {
       const T F = T(r.p[0]), K = T(r.p[1]);
-      const T x = u[0], v = u[1], gu = g[0], gv = g[1];
       const T xv2 = T(2) * x * v;
       out[0] = gu * (-v * v - F) + gv * v * v;
       out[1] = gu * (-xv2) + gv * (xv2 - F - K);
@@ -150,11 +145,8 @@ __device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g
         pacc[0] += wgt * double(gu * (T(1) - x) - gv * v);
         pacc[1] += wgt * double(-gv * v);
       }
-      break;
-    }
-    case RXN_SCHNAKENBERG: {
+    } else if constexpr (KIND == RXN_SCHNAKENBERG) {
       const T gm = T(r.p[0]), a = T(r.p[1]), b = T(r.p[2]);
-      const T x = u[0], v = u[1], gu = g[0], gv = g[1];
       const T xv2 = T(2) * x * v, xx = x * x;
       out[0] = gm * (gu * (xv2 - T(1)) - gv * xv2);
       out[1] = gm * (gu - gv) * xx;
@@ -164,11 +156,8 @@ __device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g
         pacc[1] += wgt * double(gu * gm);
         pacc[2] += wgt * double(gv * gm);
       }
-      break;
-    }
-    default: {  // Gierer-Meinhardt
+    } else {  // Gierer-Meinhardt
       const T mu_u = T(r.p[1]), s_u = T(r.p[2]), s_v = T(r.p[3]), mu_v = T(r.p[4]);
-      const T x = u[0], v = u[1], gu = g[0], gv = g[1];
       const T xv = x / v;
       out[0] = gu * (-mu_u + T(2) * s_u * xv) + gv * T(2) * s_v * x;
       out[1] = -gu * s_u * xv * xv - gv * mu_v;
@@ -179,9 +168,22 @@ __device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g
         pacc[3] += wgt * double(gv * x * x);
         pacc[4] += wgt * double(-gv * v);
       }
-      break;
     }
   }
+}
+
+// The same with the kind taken at run time.
+template <typename T, int NS>
+__device__ __forceinline__ void rxn_adjoint(const Rxn& r, const T* u, const T* g, T* out,
+                                            double wgt, double* pacc, bool want_p) {
+  switch (r.kind) {
+    case RXN_LINEAR: rxn_adjoint_k<T, NS, RXN_LINEAR>(r, u, g, out, wgt, pacc, want_p); break;
+    case RXN_FHN: rxn_adjoint_k<T, NS, RXN_FHN>(r, u, g, out, wgt, pacc, want_p); break;
+    case RXN_GRAY_SCOTT: rxn_adjoint_k<T, NS, RXN_GRAY_SCOTT>(r, u, g, out, wgt, pacc, want_p); break;
+    case RXN_SCHNAKENBERG: rxn_adjoint_k<T, NS, RXN_SCHNAKENBERG>(r, u, g, out, wgt, pacc, want_p); break;
+    case RXN_GM: rxn_adjoint_k<T, NS, RXN_GM>(r, u, g, out, wgt, pacc, want_p); break;
+    case RXN_HUXLEY_MMS: rxn_adjoint_k<T, NS, RXN_HUXLEY_MMS>(r, u, g, out, wgt, pacc, want_p); break;
+    default: rxn_adjoint_k<T, NS, RXN_FISHER_MMS>(r, u, g, out, wgt, pacc, want_p); break;
   }
 }
 
