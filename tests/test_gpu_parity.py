@@ -318,3 +318,39 @@ def test_null_state_is_rejected_on_a_live_plan():
     p = plan_for(CASES[0], "f64")
     assert C.lib().sfrde_integrate(p.handle, None, 1, 0.0, 0, None) == C.EINVAL
     p.close()
+
+
+# 1D plans (run as 2D plans with a one-point padding axis) for every boundary
+# condition, two species with different orders, forward and adjoint.
+ONE_D = [
+    W.Workload(name=f"sch1d-{bc}", bc=bc, shape=(n,), domain=(0.0, 1.0), alpha=(1.6, 1.3),
+               kappa=(0.01, 0.1), reaction="schnakenberg", params=SCH, dt=0.01, nsteps=5,
+               seed=5, init="normal", extra={"mean": [0.9, 0.9], "sd": 0.05})
+    for bc, n in (("periodic", 50), ("dirichlet", 63), ("neumann", 257))
+]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+@pytest.mark.parametrize("wl", ONE_D, ids=[c.name for c in ONE_D])
+def test_one_dimensional_plans_match_oracle(wl, dtype, tol):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 5)
+    assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
+
+
+@pytest.mark.parametrize("wl", ONE_D, ids=[c.name for c in ONE_D])
+def test_one_dimensional_adjoint_matches_oracle(wl):
+    u0 = W.initial_fields(wl)
+    wbar = np.random.default_rng(21).standard_normal(u0.shape)
+    ref = problem.gradients(wl, u0, 5, wbar)
+    p = plan_for(wl, "f64")
+    u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    ck = p.integrate(u, 5, 0.0, ckpt_every=2)
+    g0 = torch.empty_like(u)
+    gk, ga, gp = p.backward(ck, 5, 2, torch.tensor(wbar, device="cuda"), 0.0, g0)
+    torch.cuda.synchronize()
+    p.close()
+    assert problem.rel_err(g0.cpu().numpy(), ref["u0"]) <= 1e-9
+    for key, got in (("kappa", gk), ("alpha", ga), ("params", gp)):
+        r = ref[key]
+        assert np.max(np.abs(np.array(got) - r)) <= 1e-9 * max(np.max(np.abs(r)), 1e-300), key
