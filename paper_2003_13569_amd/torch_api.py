@@ -115,20 +115,23 @@ class SFRDEFunction(torch.autograd.Function):
     """u_T = integrate(u0; kappa, alpha, params) with the discrete adjoint.
 
     ``spec`` is a dict: shape, bc, h, dt, reaction, nsteps, ckpt_every,
-    dtype, scheme (t0 optional).
+    dtype, scheme (t0 optional). With ``spec["batch"] = B`` it runs an
+    ensemble plan: u0 is [B, S, ...], kappa and alpha [B, S], params [B, np].
     """
 
     @staticmethod
     def forward(ctx, u0, kappa, alpha, params, spec):
+        batch = spec.get("batch")
         plan = Plan(spec["shape"], spec["bc"], spec["h"], alpha.tolist(), kappa.tolist(),
                     spec["dt"], spec["reaction"], params.tolist(), spec.get("dtype", "f32"),
-                    spec.get("scheme", "p13"))
+                    spec.get("scheme", "p13"), batch=batch)
         n, K = int(spec["nsteps"]), int(spec.get("ckpt_every") or spec["nsteps"])
         u = u0.detach().clone().contiguous()
         ckpt = plan.integrate(u, n, spec.get("t0", 0.0), K)
         ctx.plan, ctx.ckpt, ctx.n, ctx.K = plan, ckpt, n, K
         ctx.t0 = spec.get("t0", 0.0)
         ctx.param_dtypes = (kappa.dtype, alpha.dtype, params.dtype)
+        ctx.param_shapes = (kappa.shape, alpha.shape, params.shape)
         return u
 
     @staticmethod
@@ -138,8 +141,9 @@ class SFRDEFunction(torch.autograd.Function):
         gu0 = torch.empty_like(g)
         gk, ga, gp = plan.backward(ctx.ckpt, ctx.n, ctx.K, g, ctx.t0, gu0)
         kd, ad, pd = ctx.param_dtypes
-        return (gu0, torch.tensor(gk, dtype=kd), torch.tensor(ga, dtype=ad),
-                torch.tensor(gp if gp else [], dtype=pd), None)
+        ks, as_, ps = ctx.param_shapes
+        return (gu0, torch.tensor(gk, dtype=kd).reshape(ks), torch.tensor(ga, dtype=ad).reshape(as_),
+                torch.tensor(gp if gp else [], dtype=pd).reshape(ps), None)
 
 
 def amplification(x, y, scheme="p13"):

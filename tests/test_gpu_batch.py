@@ -124,3 +124,31 @@ def test_batch_of_example2_members_reproduces_table2_rows():
         err = float(np.max(np.abs(u[b, 0].cpu().numpy() - exact)))
         assert abs(err - printed) <= 0.6e-4 * printed, (alpha, err)
     p.close()
+
+
+def test_autograd_function_on_an_ensemble_matches_members():
+    """SFRDEFunction with spec["batch"]: gradients of every member equal those
+    of that member run alone through the same function."""
+    from paper_2003_13569_amd.torch_api import SFRDEFunction
+    wl = CASES[2]
+    members = _members(wl, 2)
+    u0 = np.stack([W.initial_fields(m) for m in members])
+    wbar = np.random.default_rng(8).standard_normal(u0.shape)
+    base = dict(shape=wl.shape, bc=wl.bc, h=wl.h, dt=wl.dt, reaction=wl.reaction, nsteps=4,
+                ckpt_every=2, dtype="f64", scheme="p13")
+
+    def grads(x0, kap, alp, par, spec, w):
+        x0 = torch.tensor(x0, device="cuda", requires_grad=True)
+        kap = torch.tensor(kap, dtype=torch.float64, requires_grad=True)
+        alp = torch.tensor(alp, dtype=torch.float64, requires_grad=True)
+        par = torch.tensor(par, dtype=torch.float64, requires_grad=True)
+        uT = SFRDEFunction.apply(x0, kap, alp, par, spec)
+        (uT * torch.tensor(w, device="cuda")).sum().backward()
+        return x0.grad.cpu().numpy(), kap.grad.numpy(), alp.grad.numpy(), par.grad.numpy()
+
+    gb = grads(u0, [m.kappa for m in members], [m.alpha for m in members],
+               [m.params for m in members], dict(base, batch=2), wbar)
+    for b, m in enumerate(members):
+        g1 = grads(u0[b], m.kappa, m.alpha, m.params, base, wbar[b])
+        for x, y in zip((gb[0][b], gb[1][b], gb[2][b], gb[3][b]), g1):
+            assert np.max(np.abs(x - y)) <= 1e-10 * max(np.max(np.abs(y)), 1e-300)
