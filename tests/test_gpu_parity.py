@@ -12,6 +12,7 @@ import torch
 import workloads as W
 from oracle import problem
 from paper_2003_13569_amd import sfrde as C
+from paper_2003_13569_amd.torch_api import Plan
 from tests.gpu_util import TD, plan_for, run
 
 pytestmark = pytest.mark.gpu
@@ -354,3 +355,41 @@ def test_one_dimensional_adjoint_matches_oracle(wl):
     for key, got in (("kappa", gk), ("alpha", ga), ("params", gp)):
         r = ref[key]
         assert np.max(np.abs(np.array(got) - r)) <= 1e-9 * max(np.max(np.abs(r)), 1e-300), key
+
+
+def test_single_steps_match_integrate():
+    # sfrde_step is one step from physical data (forward transforms of the
+    # state each call): k calls agree with one k-step integrate to rounding,
+    # and a step at time t equals a one-step integrate from t0 = t.
+    wl = CASES[1]
+    u0 = W.initial_fields(wl)
+    p = plan_for(wl, "f64")
+    a = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    b = a.clone()
+    for k in range(4):
+        p.step(a, k * wl.dt)
+    p.integrate(b, 4, 0.0)
+    torch.cuda.synchronize()
+    assert problem.rel_err(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
+    h = 1.0 / 20
+    pm = Plan((20, 20), "periodic", (h, h), (1.5,), (1.0,), 0.1 * h, "huxley_mms", (), "f64")
+    x = torch.zeros((1, 20, 20), dtype=torch.float64, device="cuda")
+    y = x.clone()
+    pm.step(x, 0.3)
+    pm.integrate(y, 1, 0.3)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    pm.close()
+    p.close()
+
+
+def test_checkpoint_and_workspace_sizes():
+    wl = CASES[6]
+    p = plan_for(wl, "f32")
+    field = wl.nspecies * wl.npoints * 4
+    assert p.ckpt_bytes(10, 3) == C.CKPT_HEADER_BYTES + 4 * field
+    assert p.ckpt_bytes(9, 3) == C.CKPT_HEADER_BYTES + 3 * field
+    assert p.workspace_bytes() >= 4 * field  # P, u_hat, c_tilde, acc at least
+    with pytest.raises(C.SfrdeError):
+        p.ckpt_bytes(10, 0)
+    p.close()
