@@ -93,6 +93,20 @@ def test_batch_adjoint_matches_oracle_per_member():
     p.close()
 
 
+def test_batch_exponential_scheme_matches_oracle():
+    wl = CASES[4].replace(scheme="exp")  # 3D Dirichlet, Cox-Matthews coefficients
+    members = _members(wl, 2)
+    u0 = np.stack([W.initial_fields(m) for m in members])
+    p = _batch_plan(members, "f64")
+    u = torch.tensor(u0, device="cuda")
+    p.integrate(u, 4, 0.0)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    p.close()
+    for b, m in enumerate(members):
+        assert problem.rel_err(got[b], problem.run(m, u0[b], 4)) <= 1e-10
+
+
 def test_batch_checkpoint_resume_continues_every_member():
     wl = CASES[6]
     members = _members(wl, 2)

@@ -101,9 +101,11 @@ DENSE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("scheme", ["p13", "exp"])
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
 @pytest.mark.parametrize("wl", DENSE_CASES, ids=[c.name for c in DENSE_CASES])
-def test_dense_axes_match_oracle(wl, dtype, tol):
+def test_dense_axes_match_oracle(wl, dtype, tol, scheme):
+    wl = wl.replace(scheme=scheme)
     u0 = W.initial_fields(wl)
     ref = problem.run(wl, u0, 5)
     assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
