@@ -1351,10 +1351,15 @@ int sfrde_plan_batch(sfrde_plan_t* out, int32_t batch, int32_t ndim, const int64
     return fail(SFRDE_EINVAL, "batch %d outside [1, %d]", batch, MAX_BATCH);
   if (!alpha || !kappa) return fail(SFRDE_EINVAL, "alpha and kappa must not be NULL");
   if (nparams > 0 && !params) return fail(SFRDE_EINVAL, "params must not be NULL");
-  for (int b = 0; b < batch; ++b)
-    TRY(validate(ndim, n, bc, h, nspecies, alpha + (size_t)b * nspecies,
-                 kappa + (size_t)b * nspecies, dt, reaction, nparams,
-                 params ? params + (size_t)b * nparams : nullptr, dtype, scheme));
+  for (int b = 0; b < batch; ++b) {
+    const int rc = validate(ndim, n, bc, h, nspecies, alpha + (size_t)b * nspecies,
+                            kappa + (size_t)b * nspecies, dt, reaction, nparams,
+                            params ? params + (size_t)b * nparams : nullptr, dtype, scheme);
+    if (rc != SFRDE_OK) {
+      if (batch > 1) g_err += " (ensemble member " + std::to_string(b) + ")";
+      return rc;
+    }
+  }
   sfrde_plan_s* p = new (std::nothrow) sfrde_plan_s();
   if (!p) return fail(SFRDE_ENOMEM, "host allocation of the plan failed");
   // A 1D plan runs as a 2D one whose second axis has one point (eigenvalue

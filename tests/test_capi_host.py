@@ -131,3 +131,16 @@ def test_stability_calls_validate_without_a_device():
     assert L.sfrde_stability_boundary(0, 2, None, 8, None, None, None) == C.EINVAL
     assert L.sfrde_stability_boundary(2, 2, None, 8, None, None, None) == C.EINVAL
     assert L.sfrde_stability_boundary(0, 0, None, 8, None, None, None) == C.OK
+
+
+def test_ensemble_plan_validates_every_member_without_a_device():
+    kw = dict(batch=3, ndim=2, n=[8, 6], bc=2, h=[0.1, 0.1], nspecies=2,
+              alpha=[1.5, 1.5, 1.6, 1.6, 1.7, 2.5], kappa=[0.01, 0.02] * 3, dt=0.1,
+              reaction=3, nparams=3, params=[1.0, 0.1, 0.9] * 3, dtype=1, scheme=0)
+    with pytest.raises(C.SfrdeError) as ei:
+        C.sfrde_plan_batch(**kw)
+    assert ei.value.code == C.EINVAL and "member 2" in C.sfrde_last_error()
+    for field, value in (("batch", 0), ("batch", 70000)):
+        with pytest.raises(C.SfrdeError) as ei:
+            C.sfrde_plan_batch(**dict(kw, alpha=[1.5] * 6, **{field: value}))
+        assert ei.value.code == C.EINVAL
