@@ -1,6 +1,7 @@
 // Device kernels of the ETDRK4 step.
 //
-// Every field is [S][total] with x fastest. A kernel works on "line tiles":
+// Every field is [S][total] with x fastest (ensembles: [member][S][total], the
+// member taken from blockIdx.y). A kernel works on "line tiles":
 // W lines along one axis (length n, stride `inner`), staged in LDS as
 // buf[s][j][w] (j along the axis, w the line within the tile). Per-axis
 // transforms are products with the axis matrix M (forward, unnormalised):

@@ -441,7 +441,7 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   ax.fb_off = (int)tile_bytes;
   size_t lds = tile_bytes + std::max(fold_bytes, res_bytes);
   lds = std::max<size_t>(lds, (size_t)threads * sizeof(double));
-  if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: keep the dense kernels
+  if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: library products or dense kernels
   p->lds_m[axis] = lds;
   // persistent grid: as many blocks as fit on the CUs at once
   const long long per_cu = 1;
