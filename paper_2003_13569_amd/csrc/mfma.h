@@ -670,35 +670,49 @@ __device__ __forceinline__ void xadj_reaction_vec(const StageArgs<float>& a, flo
   const Geom& g = a.g;
   const TileRef tr = tile_ref(g, tile);
   const bool want_p = a.rp_acc != nullptr;
-  const int sh = IO::vshift(g);  // vectors per species 2^sh
+  const int sh = IO::vshift(g);  // vectors per species 2^sh, a multiple of 512
   const int n = g.n;
-  const long long line0 = tile * 32;
-  const int n1 = (int)a.n1;
-  const bool three = a.n2 > 1;
+  const int line0 = (int)(tile * 32);  // line index = y + n1 z (< 2^20)
+  const int n1 = (int)a.n1, n2 = (int)a.n2;
+  const bool three = n2 > 1;
   const int nv = 1 << sh;
+  const float* sp = a.st_phys + (long long)a.mode * NS * g.total + tr.base;
+  // the stored stage values of the next vector are loaded while this one is
+  // computed (past the last vector the last one is loaded again)
+  float4 cur[NS], nxt[NS];
+  {
+    int go, lo;
+    IO::coords(g, 0, threadIdx.x, go, lo);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+      cur[s] = *reinterpret_cast<const float4*>(sp + (long long)s * g.total + go);
+  }
 #pragma unroll 1
   for (int q = threadIdx.x; q < nv; q += 512) {
+    {
+      const int qn = q + 512 < nv ? q + 512 : q;
+      int go, lo;
+      IO::coords(g, 0, qn, go, lo);
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        nxt[s] = *reinterpret_cast<const float4*>(sp + (long long)s * g.total + go);
+    }
     int go, lo;
     IO::coords(g, 0, q, go, lo);
     const int line = go / n, j = go - line * n;
-    const long long idx = tr.base + go;
-    float4 u4[NS];
-#pragma unroll
-    for (int s = 0; s < NS; ++s)
-      u4[s] = *reinterpret_cast<const float4*>(a.st_phys + ((long long)a.mode * NS + s) * g.total + idx);
     double wl = 1.0;
     if (a.neumann) {
-      const long long gl = line0 + line;  // line index = y + n1 z
-      const int y = (int)(gl % n1), z = three ? (int)(gl / n1) : 0;
+      const int gl = line0 + line;
+      const int y = gl % n1, z = three ? gl / n1 : 0;
       if (y == 0 || y == n1 - 1) wl *= 0.5;
-      if (three && (z == 0 || z == (int)a.n2 - 1)) wl *= 0.5;
+      if (three && (z == 0 || z == n2 - 1)) wl *= 0.5;
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       float u[NS], gg[NS], o[NS];
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        u[s] = vget<float>(u4[s], e);
+        u[s] = vget<float>(cur[s], e);
         gg[s] = buf[lo + s * n * IO::P + e * IO::P];
       }
       const double w = a.neumann && (j + e == 0 || j + e == n - 1) ? 0.5 * wl : wl;
@@ -706,6 +720,8 @@ __device__ __forceinline__ void xadj_reaction_vec(const StageArgs<float>& a, flo
 #pragma unroll
       for (int s = 0; s < NS; ++s) buf[lo + s * n * IO::P + e * IO::P] = o[s];
     }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) cur[s] = nxt[s];
   }
 }
 
