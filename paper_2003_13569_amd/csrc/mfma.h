@@ -1386,9 +1386,25 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
   if (bad) a.flag[0] = 1;
 }
 
+// A contiguous run of tiles for this block, [t0, t1), runs balanced over the
+// grid (gridDim.x <= ntiles, so no run is empty). With runs instead of a
+// stride of gridDim.x, the tiles in flight at one time lie spread over the
+// whole field rather than in one slab of it, which the strided rows of a
+// last-axis tile read at a higher HBM rate.
+struct TileRun {
+  long long t0, t1;
+  __device__ __forceinline__ explicit TileRun(long long ntiles)
+      : t0((long long)blockIdx.x * ntiles / gridDim.x),
+        t1(((long long)blockIdx.x + 1) * ntiles / gridDim.x) {}
+  __device__ __forceinline__ long long next(long long tile) const {
+    return tile + 1 < t1 ? tile + 1 : t1 - 1;
+  }
+};
+
 // MODE >= 0 (FAST FP32 plans whose last axis has 256 points, forward
 // stages): the stage arrays of the next tile are loaded while this one is
-// computed. MODE < 0 takes a.mode at run time.
+// computed, each block taking a run of tiles. MODE < 0 takes a.mode at run
+// time.
 template <typename T, class XF, int MODE, bool FAST>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(StageArgs<T> a, MfmaAxisDev ax) {
   to_member(a);
@@ -1399,8 +1415,9 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
   const int S = a.g.spt;
   const long long last = a.g.ntiles - 1;
   TilePipe<T, XF::W, FAST, false> pipe;
-  pipe.issue(a.g, blockIdx.x, src);
   if constexpr (FAST && MODE >= 0 && std::is_same<T, float>::value && XF::W == 32) {
+    const TileRun run(a.g.ntiles);
+    pipe.issue(a.g, run.t0, src);
     // eigenvalue tables for L formed in the kernel
     float* lam_lds = reinterpret_cast<float*>(smem_raw + a.lam_off);
     if (a.lfly) {
@@ -1410,11 +1427,11 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
                                   : (i < nx + ny ? a.lam[1][i - nx] : a.lam[2][i - nx - ny]));
     }
     StageLoads<MODE> ld;
-    ld.issue(a, blockIdx.x);
-    pipe.commit(a.g, blockIdx.x, src, buf);
+    ld.issue(a, run.t0);
+    pipe.commit(a.g, run.t0, src, buf);
     __syncthreads();
-    for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-      const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+    for (long long tile = run.t0; tile < run.t1; ++tile) {
+      const long long next = run.next(tile);
       pipe.issue(a.g, next, src);
       xf(buf, 1);
       combine_pre<MODE>(a, buf, tile, ld, lam_lds);
@@ -1432,6 +1449,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
       __syncthreads();
     }
   } else {
+    pipe.issue(a.g, blockIdx.x, src);
     pipe.commit(a.g, blockIdx.x, src, buf);
     __syncthreads();
     for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
