@@ -1449,11 +1449,12 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
       __syncthreads();
     }
   } else {
-    pipe.issue(a.g, blockIdx.x, src);
-    pipe.commit(a.g, blockIdx.x, src, buf);
+    const TileRun run(a.g.ntiles);
+    pipe.issue(a.g, run.t0, src);
+    pipe.commit(a.g, run.t0, src, buf);
     __syncthreads();
-    for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-      const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+    for (long long tile = run.t0; tile < run.t1; ++tile) {
+      const long long next = run.next(tile);
       if (!a.src) xf(buf, S);
       combine_tile<T, XF::W, FAST>(a, buf, tile);
       __syncthreads();
@@ -1504,11 +1505,11 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
 template <class XF, int MODE, bool TH>
 __device__ __forceinline__ void zadj_staged(const StageArgs<float>& a, float* buf, XF& xf,
                                             TilePipe<float, XF::W, true, false>& pipe,
-                                            const float* lam_lds, double (&acc)[4]) {
-  const long long last = a.g.ntiles - 1;
+                                            const float* lam_lds, double (&acc)[4],
+                                            const TileRun& run) {
   AdjLoads<MODE, TH> ld;
-  for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+  for (long long tile = run.t0; tile < run.t1; ++tile) {
+    const long long next = run.next(tile);
     ld.issue(a, tile);
     xf(buf, 1);
     zadj_tile32<MODE, TH, true>(a, buf, tile, lam_lds, acc, &ld);
@@ -1531,10 +1532,10 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const int S = a.g.spt;
-  const long long last = a.g.ntiles - 1;
+  const TileRun run(a.g.ntiles);
   TilePipe<T, XF::W, FAST, false> pipe;
-  pipe.issue(a.g, blockIdx.x, a.P);
-  pipe.commit(a.g, blockIdx.x, a.P, buf);
+  pipe.issue(a.g, run.t0, a.P);
+  pipe.commit(a.g, run.t0, a.P, buf);
   if constexpr (FAST && std::is_same<T, float>::value && XF::W == 32) {
     // (a per-point accumulator G, when present, is filled by the generic path)
     if (a.lfly && S == 1 && (a.thp != nullptr || a.G == nullptr)) {
@@ -1549,12 +1550,12 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
       const bool th = a.thp != nullptr;
       if constexpr (MODE >= 0) {
         if (th)
-          zadj_staged<XF, MODE, MODE <= 2>(a, buf, xf, pipe, lam_lds, acc);
+          zadj_staged<XF, MODE, MODE <= 2>(a, buf, xf, pipe, lam_lds, acc, run);
         else
-          zadj_staged<XF, MODE, false>(a, buf, xf, pipe, lam_lds, acc);
+          zadj_staged<XF, MODE, false>(a, buf, xf, pipe, lam_lds, acc, run);
       } else
-      for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-        const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+      for (long long tile = run.t0; tile < run.t1; ++tile) {
+        const long long next = run.next(tile);
         xf(buf, 1);
         if (th)
           zadj_vec<true>(a, buf, tile, lam_lds, acc);
@@ -1587,8 +1588,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
     }
   }
   __syncthreads();
-  for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+  for (long long tile = run.t0; tile < run.t1; ++tile) {
+    const long long next = run.next(tile);
     xf(buf, S);
     pw_adj_combine(a, buf, tile);
     __syncthreads();
