@@ -158,6 +158,61 @@ def time_configs(W, Plan, torch, time):
     return configs
 
 
+def time_c4_adjoint(W, Plan, torch, time):
+    """The Gierer-Meinhardt 256^2 Neumann adjoint workload at full size: loss =
+    mean over points of the squared distance of (u, v) after 200 steps from a
+    target run with perturbed orders, diffusion and source; checkpoints every
+    20 steps; gradients of u0, kappa, alpha and the reaction parameters. The
+    forward and the backward are timed in FP32 and FP64 (warm plans)."""
+    c = W.C4_GM_ADJ
+    tg = c.extra["target"]
+    u0 = W.initial_fields(c)
+    out, grads = {}, {}
+    for dt_c in ("f32", "f64"):
+        td = torch.float32 if dt_c == "f32" else torch.float64
+        pt = Plan(c.shape, c.bc, c.h, tg["alpha"], tg["kappa"], c.dt, c.reaction, tg["params"],
+                  dt_c, c.scheme)
+        target = torch.tensor(u0, dtype=td, device="cuda")
+        pt.integrate(target, c.nsteps)
+        pt.close()
+        pc = Plan(c.shape, c.bc, c.h, c.alpha, c.kappa, c.dt, c.reaction, c.params, dt_c,
+                  c.scheme)
+        u = torch.tensor(u0, dtype=td, device="cuda")
+        ck = pc.integrate(u.clone(), c.nsteps, 0.0, ckpt_every=c.ckpt_every)  # warm-up
+        g = torch.zeros_like(u)
+        g0 = torch.empty_like(u)
+        pc.backward(ck, c.nsteps, c.ckpt_every, g, 0.0, g0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pc.integrate(u.clone(), c.nsteps)
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t0
+        uc = u.clone()
+        t0 = time.perf_counter()
+        ck = pc.integrate(uc, c.nsteps, 0.0, ckpt_every=c.ckpt_every)
+        torch.cuda.synchronize()
+        t_fc = time.perf_counter() - t0
+        g = (2.0 / c.npoints) * (uc - target)
+        t0 = time.perf_counter()
+        gk, ga, gp = pc.backward(ck, c.nsteps, c.ckpt_every, g, 0.0, g0)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        loss = float(((uc.double() - target.double()) ** 2).sum() / c.npoints)
+        grads[dt_c] = list(gk) + list(ga) + list(gp)
+        out[dt_c] = {"forward_s": round(t_f, 4), "forward_with_ckpt_s": round(t_fc, 4),
+                     "backward_s": round(t_b, 4), "ratio": round(t_b / t_f, 3), "loss": loss,
+                     "workspace_mb": round(pc.workspace_bytes() / 1e6, 1),
+                     "checkpoint_mb": round(ck.numel() / 1e6, 1)}
+        print(f"[bench] {c.name} adjoint {dt_c}: forward {t_f * 1e3:.1f} ms, backward "
+              f"{t_b * 1e3:.1f} ms ({t_b / t_f:.2f}x)", flush=True)
+        pc.close()
+        del ck, u, uc, target, g, g0
+    scale = max(abs(b) for b in grads["f64"])
+    out["fp32_vs_fp64_grad"] = max(abs(a - b) for a, b in zip(grads["f32"], grads["f64"])) / scale
+    out["workload"] = f"{c.name}: {c.nsteps} steps, checkpoints every {c.ckpt_every}"
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +226,8 @@ def main() -> int:
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-c4-adjoint", action="store_true",
+                    help="skip the Gierer-Meinhardt 256^2 adjoint timing")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the timings of the other benchmark configurations")
     ap.add_argument("--c5-adjoint", action="store_true",
@@ -437,6 +494,7 @@ def main() -> int:
 
     # ---------------------------------------------------------------- other configs
     configs = None if args.no_configs else time_configs(W, Plan, torch, time)
+    c4adj = None if args.no_c4_adjoint else time_c4_adjoint(W, Plan, torch, time)
 
     # ---------------------------------------------------------------- CPU oracle
     cpu = None
@@ -479,6 +537,7 @@ def main() -> int:
         "error": {"fp32_vs_fp64_gpu": err, "steps": args.fp64_steps} if err is not None else None,
         "adjoint": adjoint,
         "ensemble": ensemble,
+        "config4_adjoint": c4adj,
         "config5_adjoint": c5adj,
         "configs": configs,
         "roofline": roofline,

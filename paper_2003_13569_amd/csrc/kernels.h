@@ -888,19 +888,38 @@ __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, lo
   }
 }
 
-// Block-wide sum of pacc[0..np) added to rp_acc[k][blockIdx.x] (fixed order).
-__device__ __forceinline__ void block_add_partials(double* red, const double* pacc, int np,
-                                                   double* rp_acc) {
-  for (int k = 0; k < np; ++k) {
-    red[threadIdx.x] = pacc[k];
-    __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) rp_acc[(long long)k * gridDim.x + blockIdx.x] += red[0];
-    __syncthreads();
+// Block sums of the first m of v[0..M): out[k][blockIdx.x] (row stride
+// gridDim.x) receives, or with `accumulate` gains, the sum of v[k] over the
+// block. Each wave sums by lane exchanges (fixed order), then one thread per
+// value adds the wave sums in wave order: two barriers in all, rather than one
+// per halving step of an LDS tree. red: LDS of m * blockDim.x / 64 doubles,
+// free for reuse (the caller's last LDS accesses precede the first barrier).
+template <int M>
+__device__ __forceinline__ void block_sums(double* red, const double (&v)[M], int m, double* out,
+                                           bool accumulate) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    if (k >= m) break;
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[k * nw + wid] = x;
   }
+  __syncthreads();
+  if ((int)threadIdx.x < m) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[threadIdx.x * nw + w];
+    double* o = out + (long long)threadIdx.x * gridDim.x + blockIdx.x;
+    *o = accumulate ? *o + t : t;
+  }
+}
+
+// Block-wide sum of pacc[0..np) added to rp_acc[k][blockIdx.x] (fixed order).
+__device__ __forceinline__ void block_add_partials(double* red, const double (&pacc)[RXN_NP_MAX],
+                                                   int np, double* rp_acc) {
+  block_sums(red, pacc, np, rp_acc, true);
 }
 
 // ---------------------------------------------------------------- tile bodies
@@ -1167,16 +1186,7 @@ __global__ void k_greduce(CoefArgs c, const double* G, double cs, int neumann, d
       acc[2 * s + 1] += gk * 0.5 * c.kappa[s] * c.tau * pw * lnl;
     }
   }
-  for (int q = 0; q < 2 * c.S; ++q) {
-    red[threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) part[(long long)q * gridDim.x + blockIdx.x] = red[0];
-    __syncthreads();
-  }
+  block_sums(red, acc, 2 * c.S, part, false);
 }
 
 // out[r] = sum over in[r][0..len) in a fixed order (one block per row).

@@ -1569,21 +1569,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
         pipe.commit(a.g, next, a.P, buf);
         __syncthreads();
       }
-      if (th) {
-        double* red = reinterpret_cast<double*>(smem_raw);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (q >= 2 * a.S) break;
-          red[threadIdx.x] = acc[q];
-          __syncthreads();
-          for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-            if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-            __syncthreads();
-          }
-          if (threadIdx.x == 0) a.thp[(long long)q * gridDim.x + blockIdx.x] += red[0];
-          __syncthreads();
-        }
-      }
+      if (th) block_sums(reinterpret_cast<double*>(smem_raw), acc, 2 * a.S, a.thp, true);
       return;
     }
   }
