@@ -407,9 +407,13 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
     g.tpo = 1;
     g.ntiles = (g.outer + W - 1) / W;
   } else {
-    // FP32 tiles along strided axes hold one species: the species index
-    // becomes part of the outer block index (the fields are [S][total]).
-    if (f32) {
+    // Tiles along strided axes hold one species (the species index becomes
+    // part of the outer block index; the fields are [S][total]): always in
+    // FP32, whose vector paths assume it, and in FP64 when tiles of every
+    // species would give the launch (all members) fewer than two blocks per
+    // CU; otherwise FP64 tiles hold every species (faster on large grids).
+    const long long tiles_all = g.outer * ((g.inner + W - 1) / W) * p->B;
+    if (f32 || tiles_all < 2LL * p->n_cu) {
       g.outer *= p->S;
       g.spt = 1;
     }
