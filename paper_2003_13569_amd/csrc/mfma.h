@@ -1413,7 +1413,6 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const T* src = a.src ? a.src : a.P;
   const int S = a.g.spt;
-  const long long last = a.g.ntiles - 1;
   TilePipe<T, XF::W, FAST, false> pipe;
   if constexpr (FAST && MODE >= 0 && std::is_same<T, float>::value && XF::W == 32) {
     const TileRun run(a.g.ntiles);

@@ -409,11 +409,12 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   } else {
     // Tiles along strided axes hold one species (the species index becomes
     // part of the outer block index; the fields are [S][total]): always in
-    // FP32, whose vector paths assume it, and in FP64 when tiles of every
-    // species would give the launch (all members) fewer than two blocks per
-    // CU; otherwise FP64 tiles hold every species (faster on large grids).
+    // FP32, whose vector paths assume it, and in FP64 when the launch (all
+    // members) split by species still has at most one block per CU, i.e.
+    // leaves CUs idle otherwise; FP64 tiles of every species are faster
+    // once the blocks outnumber the CUs.
     const long long tiles_all = g.outer * ((g.inner + W - 1) / W) * p->B;
-    if (f32 || tiles_all < 2LL * p->n_cu) {
+    if (f32 || tiles_all * p->S <= (long long)p->n_cu) {
       g.outer *= p->S;
       g.spt = 1;
     }
