@@ -166,3 +166,34 @@ def test_autograd_function_on_an_ensemble_matches_members():
         g1 = grads(u0[b], m.kappa, m.alpha, m.params, base, wbar[b])
         for x, y in zip((gb[0][b], gb[1][b], gb[2][b], gb[3][b]), g1):
             assert np.max(np.abs(x - y)) <= 1e-10 * max(np.max(np.abs(y)), 1e-300)
+
+
+def test_large_fp64_ensemble_of_small_grids_matches_oracle():
+    """48 members of a small 2D FP64 problem in one plan. A single member's
+    strided-axis tiles hold one species (too few blocks otherwise); with 48
+    members the launch has enough blocks and the tiles hold both species. Both
+    layouts must give each member's oracle result."""
+    wl = CASES[0]  # FitzHugh-Nagumo, Neumann, 37 x 45
+    B = 48
+    members = [wl.replace(alpha=(1.2 + 0.8 * b / (B - 1),) * 2,
+                          kappa=(wl.kappa[0] * (1.0 + 0.05 * b), wl.kappa[1]), seed=wl.seed + b)
+               for b in range(B)]
+    u0 = np.stack([W.initial_fields(m) for m in members])
+    p = _batch_plan(members, "f64")
+    u = torch.tensor(u0, device="cuda")
+    p.integrate(u, 3, 0.0)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy()
+    p.close()
+    for b in range(0, B, 6):
+        ref = problem.run(members[b], u0[b], 3)
+        assert problem.rel_err(got[b], ref) <= 1e-10, (b, problem.rel_err(got[b], ref))
+    # the same members alone (species-split tiles) agree with the ensemble
+    for b in (0, B - 1):
+        m = members[b]
+        q = Plan(m.shape, m.bc, m.h, m.alpha, m.kappa, m.dt, m.reaction, m.params, "f64", m.scheme)
+        v = torch.tensor(u0[b], device="cuda")
+        q.integrate(v, 3, 0.0)
+        torch.cuda.synchronize()
+        assert problem.rel_err(v.cpu().numpy(), got[b]) <= 1e-12
+        q.close()
