@@ -987,13 +987,15 @@ struct AdjLoads {
     if (MODE == 2) return j == 0 ? a.ahat : j == 1 ? a.aacc : j == 2 ? a.gu : a.st_uhat;
     return a.aacc;
   }
+  // arrays j0 .. j1-1
+  template <int J0 = 0, int J1 = NQ>
   __device__ __forceinline__ void issue(const StageArgs<float>& a, long long tile) {
     using IO = TileIO<float, 32>;
     const TileRef tr = tile_ref(a.g, tile);
     const long long inner = a.g.inner;
     const long long i0 = tr.base + IO::row0() * inner + IO::lane4();
 #pragma unroll
-    for (int j = 0; j < NQ; ++j) {
+    for (int j = J0; j < (J1 < NQ ? J1 : NQ); ++j) {
       const float* p = src(a, j);
 #pragma unroll
       for (int k = 0; k < IO::MAXK; ++k)
@@ -1507,10 +1509,14 @@ __device__ __forceinline__ void zadj_staged(const StageArgs<float>& a, float* bu
                                             const float* lam_lds, double (&acc)[4],
                                             const TileRun& run) {
   AdjLoads<MODE, TH> ld;
+  // with the kappa/alpha terms, the stored stage arrays are loaded after the
+  // forward transform (fewer registers live across it)
+  constexpr int NE = TH ? 2 : AdjLoads<MODE, TH>::NQ;
   for (long long tile = run.t0; tile < run.t1; ++tile) {
     const long long next = run.next(tile);
-    ld.issue(a, tile);
+    ld.template issue<0, NE>(a, tile);
     xf(buf, 1);
+    ld.template issue<NE, AdjLoads<MODE, TH>::NQ>(a, tile);
     zadj_tile32<MODE, TH, true>(a, buf, tile, lam_lds, acc, &ld);
     __syncthreads();
     pipe.issue(a.g, next, a.P);
