@@ -163,7 +163,11 @@ int64_t sfrde_ckpt_bytes(sfrde_plan_t plan, int64_t nsteps, int64_t ckpt_every);
 /* Continue from checkpoint slot `slot` (the spectral state before step
  * slot*K of the run that wrote ckpt): runs nsteps steps from t0 into state.
  * Bitwise identical to the original run's continuation. ckpt_out as in
- * sfrde_integrate (may be NULL). */
+ * sfrde_integrate (may be NULL). The checkpoint header records the writer's
+ * species count, dtype, dimension, boundary condition, ensemble size and
+ * unknowns per axis; ESTATE if any differs from this plan's (another shape
+ * or boundary condition is another spectral basis) or slot is past the last
+ * stored state. */
 int sfrde_resume(sfrde_plan_t plan, const void* ckpt, int64_t slot, void* state,
                  int64_t nsteps, double t0, int64_t ckpt_every, void* ckpt_out);
 
@@ -178,7 +182,8 @@ int sfrde_resume(sfrde_plan_t plan, const void* ckpt, int64_t slot, void* state,
  *   grad_kappa  host double[S] (NULL: skip)   dLoss/dkappa_s
  *   grad_alpha  host double[S] (NULL: skip)   dLoss/dalpha_s
  *   grad_params host double[nparams] (NULL: skip)
- * Errors: ESTATE if the checkpoint does not match. */
+ * Errors: ESTATE if the checkpoint does not match (header fields as for
+ * sfrde_resume, or another ckpt_every, or fewer than nsteps steps). */
 int sfrde_backward(sfrde_plan_t plan, const void* ckpt, int64_t nsteps,
                    int64_t ckpt_every, double t0, const void* grad_uT, void* grad_u0,
                    double* grad_kappa, double* grad_alpha, double* grad_params);

@@ -140,6 +140,34 @@ SFRDE_HD inline void coef_values(int scheme, double L, double tau, double* out) 
   coefs(scheme, L, tau, out);
 }
 
+// The plan's coefficient tables hold the decrements 1 - R and 1 - Q in the
+// C_R and C_Q slots, the phi functions as they are. R and Q multiply the
+// retained spectral state every step and lie within about L of 1 for the
+// slowly decaying modes: stored as values, their rounding (half an ulp of 1,
+// the same in every step) would change each such mode's decay rate by a
+// relative 2^-25 / L. Stored as decrements they keep full relative
+// precision, and the combine forms R x as x - (1 - R) x.
+//   P13:  1 - R13 = L (24 + 6L + L^2) / D,  1 - Q13 = L (96 + 12L + L^2) / Dh
+//         (L < 1; above, 1 - R13 and 1 - Q13 from the values, no cancellation)
+//   EXP:  1 - e^-L = -expm1(-L),  1 - e^-L/2 = -expm1(-L/2)
+SFRDE_HD inline void coef_table_values(int scheme, double L, double tau, double* out) {
+  coefs(scheme, L, tau, out);
+  if (scheme == 0) {
+    if (L < 1.0) {
+      const double D = 24.0 + L * (18.0 + L * (6.0 + L));
+      const double Dh = 192.0 + L * (72.0 + L * (12.0 + L));
+      out[C_R] = L * (24.0 + L * (6.0 + L)) / D;
+      out[C_Q] = L * (96.0 + L * (12.0 + L)) / Dh;
+    } else {
+      out[C_R] = 1.0 - out[C_R];
+      out[C_Q] = 1.0 - out[C_Q];
+    }
+  } else {
+    out[C_R] = -expm1(-L);
+    out[C_Q] = -expm1(-0.5 * L);
+  }
+}
+
 // Per-axis eigenvalue at spectral index k (0-based, the library's order).
 SFRDE_HD inline double axis_eigenvalue(int bc, long n, double h, long k) {
   const double pi = 3.14159265358979323846;

@@ -505,8 +505,10 @@ __device__ __forceinline__ bool pw_reaction(const StageArgs<T>& a, T* buf, long 
   }
 }
 
-// Coefficients a forward stage needs, as c0..c3:
-//   stage 0: Q, phi, R, phi1;  stage 1: Q, phi, phi2;  stage 2: -, phi, phi2;
+// Coefficients a forward stage needs, as c0..c3, with the decrements
+// dQ = 1 - Q and dR = 1 - R in place of Q and R (the combine forms Q x as
+// x - dQ x, which keeps the slow modes' decay exact to the rounding of dQ):
+//   stage 0: dQ, phi, dR, phi1;  stage 1: dQ, phi, phi2;  stage 2: -, phi, phi2;
 //   stage 3: -, -, phi3.
 template <typename T>
 __device__ __forceinline__ T recip(T x) {
@@ -519,12 +521,13 @@ __device__ __forceinline__ float recip<float>(float x) {
 
 // P13 coefficients (Section 4) of one L in the field precision. The
 // denominators D = 24 + 18L + 6L^2 + L^3 and Dh = 192 + 72L + 12L^2 + L^3 are
-// sums of positive terms for L >= 0. R13 and Q13 multiply the retained
-// spectral state every step, so for L < 1 they are formed as
-//   R13 = 1 - L (24 + 6L + L^2) / D,   Q13 = 1 - L (96 + 12L + L^2) / Dh,
-// exact at L = 0 (the mean of a Neumann or periodic field is not damped by a
-// rounded reciprocal) and accurate to the rounding of 1 for small L. FP32
-// tables clamp L far below overflow of L^3.
+// sums of positive terms for L >= 0. The decrements of R13 and Q13 are, for
+// L < 1,
+//   1 - R13 = L (24 + 6L + L^2) / D,   1 - Q13 = L (96 + 12L + L^2) / Dh,
+// exactly 0 at L = 0 (the mean of a Neumann or periodic field is not damped)
+// and accurate to their own relative rounding for small L; for L >= 1 they
+// are 1 minus the values (no cancellation there). FP32 tables clamp L far
+// below overflow of L^3.
 template <typename T>
 __device__ __forceinline__ void stage_coefs_L(int mode, T L, T tau, T& c0, T& c1, T& c2, T& c3) {
   const T iD = recip<T>(T(24) + L * (T(18) + L * (T(6) + L)));
@@ -536,13 +539,19 @@ __device__ __forceinline__ void stage_coefs_L(int mode, T L, T tau, T& c0, T& c1
   const T iDh = recip<T>(T(192) + L * (T(72) + L * (T(12) + L)));
   const T ph = T(96) + L * (T(12) + L);
   c1 = tau * ph * iDh;
-  if (mode <= 1) c0 = small ? T(1) - L * ph * iDh : T(24) * (T(8) - L) * iDh;
+  if (mode <= 1) c0 = small ? L * ph * iDh : T(1) - T(24) * (T(8) - L) * iDh;
   if (mode != 0) {
     c2 = T(2) * tau * (T(4) + L) * iD;
     return;
   }
-  c2 = small ? T(1) - L * (T(24) + L * (T(6) + L)) * iD : (T(24) - T(6) * L) * iD;
+  c2 = small ? L * (T(24) + L * (T(6) + L)) * iD : T(1) - (T(24) - T(6) * L) * iD;
   c3 = tau * (T(4) - L) * iD;
+}
+
+// x - d x: a coefficient near 1 applied through its decrement d (one rounding).
+template <typename T>
+__device__ __forceinline__ T dec_mul(T d, T x) {
+  return fma(-d, x, x);
 }
 
 template <typename T>
@@ -601,16 +610,16 @@ __device__ __forceinline__ void pw_combine(const StageArgs<T>& a, T* buf, long l
           const T uh = a.uhat[i];
           if (a.st_uhat) a.st_uhat[i] = uh;
           if (a.st_fhat) a.st_fhat[i] = fh;
-          const T av = c0 * uh + c1 * fh;
-          a.ctil[i] = c0 * av - c1 * fh;
-          a.acc[i] = c2 * uh + c3 * fh;
+          const T av = dec_mul(c0, uh) + c1 * fh;
+          a.ctil[i] = dec_mul(c0, av) - c1 * fh;
+          a.acc[i] = dec_mul(c2, uh) + c3 * fh;
           out = av;
           break;
         }
         case 1: {
           if (a.st_fhat) a.st_fhat[1 * cst + i] = fh;
           const T uh = a.uhat[i];
-          out = c0 * uh + c1 * fh;
+          out = dec_mul(c0, uh) + c1 * fh;
           a.acc[i] += c2 * fh;
           break;
         }
@@ -691,12 +700,12 @@ __device__ __forceinline__ void combine_vec(const StageArgs<T>& a, T* buf, const
       const T f = vget<T>(fh, e);
       if (MODE == 0) {
         const T u = vget<T>(uh, e);
-        const T av = c0 * u + c1 * f;
-        vset<T>(o0, e, c0 * av - c1 * f);
-        vset<T>(o1, e, c2 * u + c3 * f);
+        const T av = dec_mul(c0, u) + c1 * f;
+        vset<T>(o0, e, dec_mul(c0, av) - c1 * f);
+        vset<T>(o1, e, dec_mul(c2, u) + c3 * f);
         vset<T>(out, e, cs * av);
       } else if (MODE == 1) {
-        vset<T>(out, e, cs * (c0 * vget<T>(uh, e) + c1 * f));
+        vset<T>(out, e, cs * (dec_mul(c0, vget<T>(uh, e)) + c1 * f));
         vset<T>(o1, e, vget<T>(ac, e) + c2 * f);
       } else if (MODE == 2) {
         vset<T>(out, e, cs * (vget<T>(ct, e) + T(2) * c1 * f));
@@ -810,8 +819,10 @@ __device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, l
 //   st 1 (b): aacc += Q X; out = phi2 z + phi X
 //   st 2 (a): A = ahat + X; aacc += Q A; out = gu + phi A
 //   st 3 (u): z <- aacc + X; out = phi3 z (or z itself at the first step)
-// G accumulates, per mode, y * g'(L) * x over every coefficient application
-// y_out = g(L) x of the forward step, for the kappa and alpha gradients.
+// R and Q are applied through the tables' decrements 1 - R, 1 - Q as in the
+// forward combine. G accumulates, per mode, y * g'(L) * x over every
+// coefficient application y_out = g(L) x of the forward step, for the kappa
+// and alpha gradients.
 template <typename T>
 __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
@@ -835,16 +846,16 @@ __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, lo
       switch (a.mode) {
         case 0: {
           const T z = a.zh[i];
-          const T cQ = cf[C_Q * cst], cP = cf[C_PHI * cst];
-          a.aacc[i] = cf[C_R * cst] * z;
-          a.ahat[i] = cQ * X;
+          const T dQ = cf[C_Q * cst], cP = cf[C_PHI * cst];
+          a.aacc[i] = dec_mul(cf[C_R * cst], z);
+          a.ahat[i] = dec_mul(dQ, X);
           a.gu[i] = cf[C_PHI1 * cst] * z - cP * X;
           out = cf[C_PHI2 * cst] * z + T(2) * cP * X;
           if (a.G) {
             const T uh = a.st_uhat[i];
             const T fu = a.st_fhat[0 * cst + i], fa = a.st_fhat[1 * cst + i];
             const T fb = a.st_fhat[2 * cst + i], fc = a.st_fhat[3 * cst + i];
-            const T ah = cQ * uh + cP * fu;
+            const T ah = dec_mul(dQ, uh) + cP * fu;
             const T s1 = dc[C_R * cst] * uh + dc[C_PHI1 * cst] * fu +
                          dc[C_PHI2 * cst] * (fa + fb) + dc[C_PHI3 * cst] * fc;
             const T s2 = dc[C_Q * cst] * ah + dc[C_PHI * cst] * (T(2) * fb - fu);
@@ -854,7 +865,7 @@ __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, lo
         }
         case 1: {
           const T z = a.zh[i];
-          a.aacc[i] += cf[C_Q * cst] * X;
+          a.aacc[i] += dec_mul(cf[C_Q * cst], X);
           out = cf[C_PHI2 * cst] * z + cf[C_PHI * cst] * X;
           if (a.G) {
             const T uh = a.st_uhat[i], fa = a.st_fhat[1 * cst + i];
@@ -864,7 +875,7 @@ __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, lo
         }
         case 2: {
           const T A = a.ahat[i] + X;
-          a.aacc[i] += cf[C_Q * cst] * A;
+          a.aacc[i] += dec_mul(cf[C_Q * cst], A);
           out = a.gu[i] + cf[C_PHI * cst] * A;
           if (a.G) {
             const T uh = a.st_uhat[i], fu = a.st_fhat[0 * cst + i];
@@ -1159,7 +1170,7 @@ __global__ void k_coefs(CoefArgs c, T* out) {
       if (c.deriv)
         coef_derivs(c.scheme, L, c.tau, v);
       else
-        coef_values(c.scheme, L, c.tau, v);
+        coef_table_values(c.scheme, L, c.tau, v);
       for (int q = 0; q < NCOEF; ++q) out[((long long)q * c.S + s) * c.total + idx] = T(v[q]);
     }
   }
@@ -1211,13 +1222,15 @@ __global__ void k_fill(T* p, long long n, T v) {
     p[i] = v;
 }
 
-// Checkpoint header: eight 64-bit words, lane i writes word i.
-__global__ void k_header(long long* h, long long a0, long long a1, long long a2, long long a3,
-                         long long a4, long long a5, long long a6, long long a7, long long a8) {
+// Checkpoint header: CKPT_WORDS 64-bit words passed by value, lane i writes
+// word i.
+constexpr int CKPT_WORDS = 12;
+struct CkptHeader {
+  long long w[CKPT_WORDS];
+};
+__global__ void k_header(long long* h, CkptHeader v) {
   const int i = threadIdx.x;
-  const long long v = i == 0 ? a0 : i == 1 ? a1 : i == 2 ? a2 : i == 3 ? a3
-                    : i == 4 ? a4 : i == 5 ? a5 : i == 6 ? a6 : i == 7 ? a7 : a8;
-  if (blockIdx.x == 0 && i < 9) h[i] = v;
+  if (blockIdx.x == 0 && i < CKPT_WORDS) h[i] = v.w[i];
 }
 
 }  // namespace sfrde

@@ -902,12 +902,12 @@ __device__ __forceinline__ void combine_pre(const StageArgs<float>& a, float* bu
       const float f = vget<float>(fh, e);
       const float x1 = vget<float>(ld.r1[k], e);
       if (MODE == 0) {
-        const float av = c0 * x1 + c1 * f;
-        vset<float>(o0, e, c0 * av - c1 * f);
-        vset<float>(o1, e, c2 * x1 + c3 * f);
+        const float av = dec_mul(c0, x1) + c1 * f;
+        vset<float>(o0, e, dec_mul(c0, av) - c1 * f);
+        vset<float>(o1, e, dec_mul(c2, x1) + c3 * f);
         vset<float>(out, e, cs * av);
       } else if (MODE == 1) {
-        vset<float>(out, e, cs * (c0 * x1 + c1 * f));
+        vset<float>(out, e, cs * (dec_mul(c0, x1) + c1 * f));
         vset<float>(o1, e, vget<float>(ld.r2[k], e) + c2 * f);
       } else if (MODE == 2) {
         vset<float>(out, e, cs * (vget<float>(ld.r2[k], e) + 2.f * c1 * f));
@@ -1237,12 +1237,12 @@ __device__ __forceinline__ void combine_tile32(const StageArgs<float>& a, float*
       const float f = vget<float>(fh, e);
       if (MODE == 0) {
         const float u = vget<float>(uh, e);
-        const float av = c0 * u + c1 * f;
-        vset<float>(o0, e, c0 * av - c1 * f);
-        vset<float>(o1, e, c2 * u + c3 * f);
+        const float av = dec_mul(c0, u) + c1 * f;
+        vset<float>(o0, e, dec_mul(c0, av) - c1 * f);
+        vset<float>(o1, e, dec_mul(c2, u) + c3 * f);
         vset<float>(out, e, cs * av);
       } else if (MODE == 1) {
-        vset<float>(out, e, cs * (c0 * vget<float>(uh, e) + c1 * f));
+        vset<float>(out, e, cs * (dec_mul(c0, vget<float>(uh, e)) + c1 * f));
         vset<float>(o1, e, vget<float>(ac, e) + c2 * f);
       } else if (MODE == 2) {
         vset<float>(out, e, cs * (vget<float>(ct, e) + 2.f * c1 * f));

@@ -833,22 +833,46 @@ int fill(sfrde_plan_s* p, T* ptr, long long n, T v) {
   return SFRDE_OK;
 }
 
+// Checkpoint header words: magic, nsteps, K, S, total, dtype, ndim, bc, B,
+// then the unknowns per axis n[0..2] (a transposed shape or another
+// boundary condition has another spectral basis and must not be resumed).
+CkptHeader header_words(const sfrde_plan_s* p, long long nsteps, long long K) {
+  CkptHeader h{};
+  const long long w[CKPT_WORDS] = {CKPT_MAGIC, nsteps, K, (long long)p->S, p->total,
+                                   (long long)p->dtype, (long long)p->ndim, (long long)p->bc,
+                                   (long long)p->B, p->n[0], p->n[1], p->n[2]};
+  for (int i = 0; i < CKPT_WORDS; ++i) h.w[i] = w[i];
+  return h;
+}
+
 int write_header(sfrde_plan_s* p, void* ckpt, long long nsteps, long long K) {
-  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, p->stream, (long long*)ckpt, CKPT_MAGIC,
-                     nsteps, K, (long long)p->S, p->total, (long long)p->dtype,
-                     (long long)p->ndim, (long long)p->bc, (long long)p->B);
+  hipLaunchKernelGGL(k_header, dim3(1), dim3(64), 0, p->stream, (long long*)ckpt,
+                     header_words(p, nsteps, K));
   HIPCHECK(hipGetLastError());
   return SFRDE_OK;
 }
 
-int check_header(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K) {
-  long long h[9];
+// Reads the header of ckpt into h and checks that this plan wrote it (every
+// word but nsteps and K).
+int read_header(sfrde_plan_s* p, const void* ckpt, long long (&h)[CKPT_WORDS]) {
   HIPCHECK(hipMemcpyAsync(h, ckpt, sizeof(h), hipMemcpyDeviceToHost, p->stream));
   HIPCHECK(hipStreamSynchronize(p->stream));
   if (h[0] != CKPT_MAGIC) return fail(SFRDE_ESTATE, "checkpoint has no valid header");
-  if (h[3] != p->S || h[4] != p->total || h[5] != p->dtype || h[6] != p->ndim || h[7] != p->bc ||
-      h[8] != p->B)
-    return fail(SFRDE_ESTATE, "checkpoint was written by a plan of another shape/dtype");
+  const CkptHeader mine = header_words(p, 0, 0);
+  static const char* const what[CKPT_WORDS] = {"", "", "", "species count", "point count",
+                                               "dtype", "dimension", "boundary condition",
+                                               "ensemble size", "x size", "y size", "z size"};
+  for (int i = 3; i < CKPT_WORDS; ++i)
+    if (h[i] != mine.w[i])
+      return fail(SFRDE_ESTATE, "checkpoint was written by a plan of another %s (%lld != %lld)",
+                  what[i], h[i], mine.w[i]);
+  if (h[2] < 1 || h[1] < 1) return fail(SFRDE_ESTATE, "checkpoint header has no steps");
+  return SFRDE_OK;
+}
+
+int check_header(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K) {
+  long long h[CKPT_WORDS];
+  TRY(read_header(p, ckpt, h));
   if (h[2] != K) return fail(SFRDE_ESTATE, "checkpoint spacing %lld != %lld", h[2], K);
   if (h[1] < nsteps) return fail(SFRDE_ESTATE, "checkpoint covers %lld < %lld steps", h[1], nsteps);
   return SFRDE_OK;
@@ -1482,12 +1506,8 @@ int sfrde_resume(sfrde_plan_t p, const void* ckpt, int64_t slot, void* state, in
   if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
   if (!ckpt || !state) return fail(SFRDE_EINVAL, "ckpt and state must not be NULL");
   if (slot < 0 || nsteps < 0 || ckpt_every < 0) return fail(SFRDE_EINVAL, "negative argument");
-  long long h[9];
-  HIPCHECK(hipMemcpyAsync(h, ckpt, sizeof(h), hipMemcpyDeviceToHost, p->stream));
-  HIPCHECK(hipStreamSynchronize(p->stream));
-  if (h[0] != CKPT_MAGIC || h[3] != p->S || h[4] != p->total || h[5] != p->dtype ||
-      h[8] != p->B)
-    return fail(SFRDE_ESTATE, "checkpoint does not match this plan");
+  long long h[CKPT_WORDS];
+  TRY(read_header(p, ckpt, h));
   const long long nslots = (h[1] + h[2] - 1) / h[2];
   if (slot >= nslots) return fail(SFRDE_ESTATE, "slot %lld >= %lld slots", (long long)slot, nslots);
   if (nsteps == 0) return SFRDE_OK;

@@ -211,3 +211,30 @@ def test_config4_adjoint_full_size_matches_central_differences():
     assert _rel(gu0_32.cpu().numpy(), gu0.cpu().numpy()) <= 1e-3
     for a, b in ((gk32, gk), (ga32, ga), (gp32, gp)):
         assert np.max(np.abs(a - b)) <= 1e-3 * np.max(np.abs(b)), (a, b)
+
+
+@pytest.mark.gpu
+def test_checkpoint_of_another_shape_or_bc_is_rejected():
+    # same point count, species and dtype: a transposed grid and another
+    # boundary condition have other spectral bases
+    from paper_2003_13569_amd import sfrde as C
+    import workloads as Wk
+    base = Wk.small(Wk.C1_FHN, (24, 32), nsteps=4)
+    tr = Wk.small(Wk.C1_FHN, (32, 24), nsteps=4)
+    bc = base.replace(bc="dirichlet")
+    pa = plan_for(base, "f64")
+    u = torch.tensor(W.initial_fields(base), dtype=torch.float64, device="cuda")
+    ckpt = pa.integrate(u, 4, 0.0, ckpt_every=2)
+    for other in (tr, bc):
+        pb = plan_for(other, "f64")
+        v = torch.zeros(pb.field_shape, dtype=torch.float64, device="cuda")
+        with pytest.raises(C.SfrdeError) as ei:
+            pb.backward(ckpt, 4, 2, v)
+        assert ei.value.code == C.ESTATE
+        with pytest.raises(C.SfrdeError) as ei:
+            pb.resume(ckpt, 1, v, 2)
+        assert ei.value.code == C.ESTATE
+        pb.close()
+    # the writer itself resumes fine
+    pa.resume(ckpt, 1, u, 2, 2 * base.dt)
+    pa.close()

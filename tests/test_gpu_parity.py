@@ -158,16 +158,22 @@ def test_config5_full_size_one_step_matches_oracle(dtype, tol):
     assert problem.rel_err(run(wl, u0, 1, dtype), _C5_REF["ref"]) <= tol
 
 
-@pytest.mark.parametrize("wl,alpha", [(W.C3_SCHNAK_DIR, 1.8), (W.C5_SCHNAK_NEU, 1.2),
-                                      (W.C5_SCHNAK_NEU, 1.9)],
-                         ids=["c3-500", "c5-a1.2-1000", "c5-a1.9-1000"])
-def test_fp32_full_horizon_matches_fp64_gpu(wl, alpha):
+@pytest.mark.parametrize("wl,alpha,nsteps", [(W.C2_GS, 1.7, 500), (W.C3_SCHNAK_DIR, 1.8, None),
+                                             (W.C5_SCHNAK_NEU, 1.2, None),
+                                             (W.C5_SCHNAK_NEU, 1.9, None)],
+                         ids=["c2-500", "c3-500", "c5-a1.2-1000", "c5-a1.9-1000"])
+def test_fp32_full_horizon_matches_fp64_gpu(wl, alpha, nsteps):
     # FP32 against the FP64 GPU path (itself pinned to the oracle above) over
-    # the configuration's whole horizon.
+    # the configuration's whole horizon. The Gray-Scott run forms spots that
+    # amplify any perturbation: an FP64 run whose state is rounded to FP32
+    # once per step leaves FP64 by 2.9e-5 after its 2000 steps (6e-7 after
+    # 500), so no FP32 computation holds 2e-5 over the full horizon; it is
+    # held to it over 500 steps.
     wl = wl.replace(alpha=(alpha, alpha))
+    nsteps = nsteps or wl.nsteps
     u0 = W.initial_fields(wl)
-    a = run(wl, u0, wl.nsteps, "f32")
-    b = run(wl, u0, wl.nsteps, "f64")
+    a = run(wl, u0, nsteps, "f32")
+    b = run(wl, u0, nsteps, "f64")
     assert problem.rel_err(a, b) <= 2e-5
 
 
