@@ -188,6 +188,28 @@ int sfrde_backward(sfrde_plan_t plan, const void* ckpt, int64_t nsteps,
                    int64_t ckpt_every, double t0, const void* grad_uT, void* grad_u0,
                    double* grad_kappa, double* grad_alpha, double* grad_params);
 
+/* Allocation-free variant of sfrde_backward, for callers that cannot
+ * allocate device memory at call time (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc). Same arguments, results
+ * and errors as sfrde_backward, computed by the same kernels; the backward
+ * buffers (adjoint fields, the segment store of ckpt_every steps, gradient
+ * partials) live in one static device array of SFRDE_NOALLOC_SCRATCH_BYTES
+ * per GPU, which the library holds from its first plan on that GPU until the
+ * process ends, instead of plan memory allocated on first use. The call
+ * makes no device allocation and frees nothing.
+ * Limits: the buffers need about (5 + 9 * min(ckpt_every, nsteps)) fields
+ * of [B][S][...] dtype (plus one FP64 field and six dtype fields when the
+ * kappa/alpha gradients take the per-point path); a request that does not
+ * fit returns SFRDE_EINVAL before any device work. Plans with an axis on
+ * library products return SFRDE_EUNSUPPORTED. Every call on one GPU uses
+ * the same array: calls that overlap in time on one GPU (other threads,
+ * other streams) race and must be serialized by the caller. Nothing is
+ * carried over between calls (each call initializes what it reads). */
+#define SFRDE_NOALLOC_SCRATCH_BYTES (128LL * 1024 * 1024)
+int sfrde_backward_noalloc(sfrde_plan_t plan, const void* ckpt, int64_t nsteps,
+                           int64_t ckpt_every, double t0, const void* grad_uT, void* grad_u0,
+                           double* grad_kappa, double* grad_alpha, double* grad_params);
+
 /* Free the plan and everything it owns (waits for its stream first). */
 int sfrde_destroy(sfrde_plan_t plan);
 

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <cstdint>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -68,6 +69,34 @@ constexpr int MAX_BATCH = 65535;  // ensemble members: the launch's grid y exten
 constexpr long long RED_OUT = 2 * MAX_SPECIES * 1024 + 64;
 constexpr long long RED_PER_MEMBER = 2 * MAX_SPECIES + MAX_PARAMS;
 
+// Device memory of sfrde_backward_noalloc: one array per GPU the library
+// runs on, held until the process ends. Host code never passes `scratch`
+// itself (in host code the name is a stand-in, not a device address): it
+// uses the address hipGetSymbolAddress returns on each device, looked up
+// once per device at plan set-up.
+constexpr size_t SCRATCH_BYTES = (size_t)SFRDE_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of this device's scratch array (the device must be current).
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(SFRDE_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SFRDE_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SFRDE_OK;
+}
+
 }  // namespace
 
 struct sfrde_plan_s {
@@ -107,6 +136,10 @@ struct sfrde_plan_s {
   MfmaAxisDev mfax[3]{};
   void* mf_A[3] = {nullptr, nullptr, nullptr};
   int n_cu = 256;
+  int device = 0;
+  // the static scratch array of the plan's device (allocation-free backward)
+  void* scratch = nullptr;
+  bool noalloc = false;  // this backward call carves its buffers from scratch
   // device memory
   void* Mt[3] = {nullptr, nullptr, nullptr};
   double* lam[3] = {nullptr, nullptr, nullptr};
@@ -1068,7 +1101,55 @@ long long rp_blocks(const sfrde_plan_s* p) {
   return p->use_m[0] ? (long long)p->grid_m[0] : p->geom[0].ntiles;
 }
 
+// Bytes of the backward buffers (what ensure_backward_buffers allocates),
+// each rounded up to 256 bytes as carve_backward_buffers lays them out.
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// The backward buffers laid out in the static scratch array (no allocation;
+// the plan's own pointers are saved and restored by the caller). Fails with
+// EINVAL, before any device work, if they do not fit.
+int carve_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_theta, bool want_p) {
+  const size_t f = field_bytes(p);
+  char* base = static_cast<char*>(p->scratch);
+  size_t off = 0;
+  auto take = [&](void** ptr, size_t bytes) {
+    *ptr = base + off;
+    off += round256(bytes);
+  };
+  take(&p->Pa, f);
+  take(&p->zh, f);
+  take(&p->aacc, f);
+  take(&p->ahat, f);
+  take(&p->gu, f);
+  take(&p->seg, (size_t)seg_steps * 9 * f);
+  p->seg_steps = seg_steps;
+  p->thp = nullptr;
+  p->G = nullptr;
+  p->dcoef = nullptr;
+  p->rp_acc = nullptr;
+  bool fill_dcoef = false;
+  if (want_theta && p->thp_on) {
+    take((void**)&p->thp, (size_t)4 * p->grid_m[p->ndim - 1] * sizeof(double));
+  } else if (want_theta) {
+    take((void**)&p->G, field_elems(p) * sizeof(double));
+    take(&p->dcoef, NCOEF * f);
+    fill_dcoef = true;
+  }
+  if (want_p) take((void**)&p->rp_acc, (size_t)p->B * MAX_PARAMS * rp_blocks(p) * sizeof(double));
+  const long long need = RED_OUT + (long long)p->B * RED_PER_MEMBER;
+  take((void**)&p->red, (size_t)need * sizeof(double));
+  p->red_len = need;
+  if (off > SCRATCH_BYTES)
+    return fail(SFRDE_EINVAL,
+                "this backward needs %zu bytes of workspace; the allocation-free entry point "
+                "holds %zu (use sfrde_backward, or a smaller ckpt_every or grid)",
+                off, SCRATCH_BYTES);
+  if (fill_dcoef) TRY(coef_tables(p, 1, p->dcoef));
+  return SFRDE_OK;
+}
+
 int ensure_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_theta, bool want_p) {
+  if (p->noalloc) return carve_backward_buffers(p, seg_steps, want_theta, want_p);
   const size_t f = field_bytes(p);
   TRY(dev_alloc(p, &p->Pa, f));
   TRY(dev_alloc(p, &p->zh, f));
@@ -1111,7 +1192,13 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
   // kappa/alpha gradients formed inside the vector adjoint Z kernels (L
   // formed there too), else through the per-point accumulator G
   p->thp_on = want_theta && p->lfly && p->B == 1 && p->S <= 2 && use_fast<T>(p, p->ndim - 1, {});
-  TRY(ensure_backward_buffers(p, seg_steps, want_theta, want_p));
+  {
+    const int rc0 = ensure_backward_buffers(p, seg_steps, want_theta, want_p);
+    if (rc0 != SFRDE_OK) {
+      p->thp_on = false;
+      return rc0;
+    }
+  }
   // Buffers from an earlier call stay allocated; accumulate only what is asked.
   double* G_saved = p->G;
   if (!want_theta || p->thp_on) p->G = nullptr;
@@ -1147,7 +1234,6 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
     if (grad_u0 && (rc = launch_single<T>(p, 0, p->Pa, grad_u0, 0, 1))) break;
     const int nb = 1024;
     double* rout = p->red + RED_OUT;
-    std::vector<double> host((size_t)p->B * RED_PER_MEMBER, 0.0);
     for (int m = 0; m < p->B && rc == SFRDE_OK; ++m) {
       double* ro = rout + (size_t)m * RED_PER_MEMBER;
       if (want_theta && p->thp_on) {  // one member only (L formed in the kernels)
@@ -1172,24 +1258,32 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
       }
     }
     if (rc) break;
-    if ((want_theta || want_p) &&
-        hipMemcpyAsync(host.data(), rout, host.size() * sizeof(double), hipMemcpyDeviceToHost,
-                       p->stream) != hipSuccess) {
-      rc = fail(SFRDE_EDEVICE, "copy of gradient partials");
-      break;
-    }
     if (hipStreamSynchronize(p->stream) != hipSuccess) {
       rc = fail(SFRDE_EDEVICE, "stream synchronize");
       break;
     }
-    for (int m = 0; m < p->B; ++m) {
-      const double* hm = host.data() + (size_t)m * RED_PER_MEMBER;
-      for (int s = 0; s < p->S; ++s) {
-        if (gk) gk[m * p->S + s] = hm[2 * s];
-        if (ga) ga[m * p->S + s] = hm[2 * s + 1];
+    // the members' sums, copied in chunks through a buffer on the stack
+    constexpr int CHUNK = 64;
+    double host[CHUNK * RED_PER_MEMBER];
+    for (int m0 = 0; m0 < p->B && (want_theta || want_p); m0 += CHUNK) {
+      const int nm = std::min(CHUNK, p->B - m0);
+      if (hipMemcpyAsync(host, rout + (size_t)m0 * RED_PER_MEMBER,
+                         (size_t)nm * RED_PER_MEMBER * sizeof(double), hipMemcpyDeviceToHost,
+                         p->stream) != hipSuccess ||
+          hipStreamSynchronize(p->stream) != hipSuccess) {
+        rc = fail(SFRDE_EDEVICE, "copy of gradient partials");
+        break;
       }
-      if (want_p)
-        for (int k = 0; k < p->rxn.np; ++k) gp[m * p->rxn.np + k] = hm[2 * MAX_SPECIES + k];
+      for (int i = 0; i < nm; ++i) {
+        const int m = m0 + i;
+        const double* hm = host + (size_t)i * RED_PER_MEMBER;
+        for (int s = 0; s < p->S; ++s) {
+          if (gk) gk[m * p->S + s] = hm[2 * s];
+          if (ga) ga[m * p->S + s] = hm[2 * s + 1];
+        }
+        if (want_p)
+          for (int k = 0; k < p->rxn.np; ++k) gp[m * p->rxn.np + k] = hm[2 * MAX_SPECIES + k];
+      }
     }
   } while (0);
   p->G = G_saved;
@@ -1275,6 +1369,8 @@ int build_plan(sfrde_plan_s* p) {
   int dev = 0;
   HIPCHECK(hipGetDevice(&dev));
   HIPCHECK(hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  p->device = dev;
+  TRY(scratch_address(dev, &p->scratch));
   for (int a = 0; a < p->ndim; ++a) {
     if (p->dtype == SFRDE_F32)
       TRY(upload_matrix<float>(p, a));
@@ -1532,6 +1628,51 @@ int sfrde_backward(sfrde_plan_t p, const void* ckpt, int64_t nsteps, int64_t ckp
                              grad_alpha, grad_params);
   return backward_t<double>(p, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0, grad_kappa,
                             grad_alpha, grad_params);
+}
+
+int sfrde_backward_noalloc(sfrde_plan_t p, const void* ckpt, int64_t nsteps,
+                           int64_t ckpt_every, double t0, const void* grad_uT, void* grad_u0,
+                           double* grad_kappa, double* grad_alpha, double* grad_params) {
+  g_err.clear();
+  if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
+  if (!ckpt || !grad_uT) return fail(SFRDE_EINVAL, "ckpt and grad_uT must not be NULL");
+  if (nsteps < 1 || ckpt_every < 1) return fail(SFRDE_EINVAL, "nsteps, ckpt_every must be >= 1");
+  for (int a = 0; a < p->ndim; ++a)
+    if (p->use_g[a])
+      return fail(SFRDE_EUNSUPPORTED,
+                  "the allocation-free backward does not run plans with library-product axes");
+  if (!p->scratch) return fail(SFRDE_EDEVICE, "the plan has no scratch address");
+  TRY(check_header(p, ckpt, nsteps, ckpt_every));
+  if (p->rxn.kind >= RXN_HUXLEY_MMS && (grad_kappa || grad_alpha))
+    return fail(SFRDE_EUNSUPPORTED,
+                "kappa and alpha gradients of the manufactured sources are not implemented");
+  // the plan's own backward buffers are set aside for this call
+  void* saved[] = {p->Pa, p->zh, p->aacc, p->ahat, p->gu, p->seg, p->G, p->dcoef, p->rp_acc,
+                   p->thp, p->red};
+  const long long saved_seg = p->seg_steps, saved_red = p->red_len;
+  p->noalloc = true;
+  int rc;
+  if (p->dtype == SFRDE_F32)
+    rc = backward_t<float>(p, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0, grad_kappa,
+                           grad_alpha, grad_params);
+  else
+    rc = backward_t<double>(p, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0, grad_kappa,
+                            grad_alpha, grad_params);
+  p->noalloc = false;
+  p->Pa = saved[0];
+  p->zh = saved[1];
+  p->aacc = saved[2];
+  p->ahat = saved[3];
+  p->gu = saved[4];
+  p->seg = saved[5];
+  p->G = (double*)saved[6];
+  p->dcoef = saved[7];
+  p->rp_acc = (double*)saved[8];
+  p->thp = (double*)saved[9];
+  p->red = (double*)saved[10];
+  p->seg_steps = saved_seg;
+  p->red_len = saved_red;
+  return rc;
 }
 
 int64_t sfrde_workspace_bytes(sfrde_plan_t p) {

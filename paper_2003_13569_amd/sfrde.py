@@ -20,7 +20,7 @@ CKPT_HEADER_BYTES = 256
 MAX_PARAMS = 16
 
 EXPORTS = ("sfrde_plan", "sfrde_plan_batch", "sfrde_step", "sfrde_integrate", "sfrde_ckpt_bytes", "sfrde_resume",
-           "sfrde_backward", "sfrde_destroy", "sfrde_last_error", "sfrde_workspace_bytes",
+           "sfrde_backward", "sfrde_backward_noalloc", "sfrde_destroy", "sfrde_last_error", "sfrde_workspace_bytes",
            "sfrde_axis_eigenvalues", "sfrde_eval_coefficients", "sfrde_profile",
            "sfrde_profile_read", "sfrde_amplification", "sfrde_stability_boundary")
 KERNEL_CLASSES = ("X", "Y", "Z", "XADJ", "ZADJ", "OTHER")
@@ -62,6 +62,8 @@ def lib() -> ctypes.CDLL:
     L.sfrde_resume.restype = ctypes.c_int
     L.sfrde_backward.argtypes = [vp, vp, i64, i64, d, vp, vp, pd, pd, pd]
     L.sfrde_backward.restype = ctypes.c_int
+    L.sfrde_backward_noalloc.argtypes = [vp, vp, i64, i64, d, vp, vp, pd, pd, pd]
+    L.sfrde_backward_noalloc.restype = ctypes.c_int
     L.sfrde_destroy.argtypes = [vp]
     L.sfrde_destroy.restype = ctypes.c_int
     L.sfrde_last_error.argtypes = []
@@ -145,19 +147,33 @@ def sfrde_resume(plan, ckpt, slot, state, nsteps, t0, ckpt_every=0, ckpt_out=Non
                                      int(ckpt_every), ckpt_out), "sfrde_resume")
 
 
-def sfrde_backward(plan, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0=None, nspecies=2,
-                   nparams=0, want_kappa=True, want_alpha=True, want_params=True, batch=1):
-    """Returns (grad_kappa, grad_alpha, grad_params) as flat lists, [batch][...]
-    for ensemble plans (None if not asked)."""
+def _backward(fn, plan, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0, nspecies, nparams,
+              want_kappa, want_alpha, want_params, batch):
     gk = (ctypes.c_double * (batch * nspecies))() if want_kappa else None
     ga = (ctypes.c_double * (batch * nspecies))() if want_alpha else None
     gp = ((ctypes.c_double * max(1, batch * nparams))() if (want_params and nparams > 0)
           else None)
-    rc = lib().sfrde_backward(plan, ckpt, int(nsteps), int(ckpt_every), float(t0), grad_uT,
-                              grad_u0, gk, ga, gp)
-    _check(rc, "sfrde_backward")
+    rc = getattr(lib(), fn)(plan, ckpt, int(nsteps), int(ckpt_every), float(t0), grad_uT,
+                            grad_u0, gk, ga, gp)
+    _check(rc, fn)
     return (list(gk) if gk is not None else None, list(ga) if ga is not None else None,
             list(gp)[:batch * nparams] if gp is not None else None)
+
+
+def sfrde_backward(plan, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0=None, nspecies=2,
+                   nparams=0, want_kappa=True, want_alpha=True, want_params=True, batch=1):
+    """Returns (grad_kappa, grad_alpha, grad_params) as flat lists, [batch][...]
+    for ensemble plans (None if not asked)."""
+    return _backward("sfrde_backward", plan, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0,
+                     nspecies, nparams, want_kappa, want_alpha, want_params, batch)
+
+
+def sfrde_backward_noalloc(plan, ckpt, nsteps, ckpt_every, t0, grad_uT, grad_u0=None,
+                           nspecies=2, nparams=0, want_kappa=True, want_alpha=True,
+                           want_params=True, batch=1):
+    """sfrde_backward without device allocation (static scratch); same returns."""
+    return _backward("sfrde_backward_noalloc", plan, ckpt, nsteps, ckpt_every, t0, grad_uT,
+                     grad_u0, nspecies, nparams, want_kappa, want_alpha, want_params, batch)
 
 
 def sfrde_destroy(plan) -> int:
