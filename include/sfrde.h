@@ -25,9 +25,10 @@
  *   of the plan's dtype, x contiguous; ensemble plans (sfrde_plan_batch) put
  *   the member first, [B][S][...]. Sizes are *unknowns* per axis: N = n
  *   (periodic), n + 1 (Dirichlet), n - 1 (Neumann) intervals with spacing h.
- * - Axes of up to 256 points (255 periodic) run on hand-written matrix-core
- *   kernels; longer axes (up to 1024) run their transforms as rocBLAS matrix
- *   products around the same pointwise kernels.
+ * - Every transform runs in hand-written kernels: axes of up to 256 points
+ *   (255 periodic) on the matrix cores, periodic axes of 256, 512 and 1024
+ *   points as radix-8/4 FFTs in LDS, any other axis (up to 1024 points) as a
+ *   dense product in LDS; each fused with the same pointwise stages.
  * - n[0] is the x (fastest) extent, n[1] y, n[2] z; h[] in the same order.
  * - The caller owns every buffer passed in (state, checkpoints, gradients)
  *   and the stream; the library never frees caller memory. The plan owns its
@@ -200,8 +201,7 @@ int sfrde_backward(sfrde_plan_t plan, const void* ckpt, int64_t nsteps,
  * Limits: the buffers need about (5 + 9 * min(ckpt_every, nsteps)) fields
  * of [B][S][...] dtype (plus one FP64 field and six dtype fields when the
  * kappa/alpha gradients take the per-point path); a request that does not
- * fit returns SFRDE_EINVAL before any device work. Plans with an axis on
- * library products return SFRDE_EUNSUPPORTED. Every call on one GPU uses
+ * fit returns SFRDE_EINVAL before any device work. Every call on one GPU uses
  * the same array: calls that overlap in time on one GPU (other threads,
  * other streams) race and must be serialized by the caller. Nothing is
  * carried over between calls (each call initializes what it reads). */

@@ -20,8 +20,6 @@ FLAGS = [
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
-    # library matrix products for axes the matrix-core engine does not take
-    "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib",
 ]
 
 

@@ -1008,15 +1008,6 @@ struct DenseXf {
   __device__ __forceinline__ void operator()(T* buf, int S) { dense_transform(buf, S, *g, Mt); }
 };
 
-// No transform: the kernels below then do only their pointwise part, for
-// axes whose transforms run as library matrix products around them.
-template <typename T>
-struct NoXf {
-  const Geom* g;
-  const T* Mt;
-  __device__ __forceinline__ void operator()(T*, int) {}
-};
-
 // X kernel, forward: inverse-x, reaction, forward-x (in place on P).
 template <typename T, template <typename> class XFT = DenseXf>
 __global__ __launch_bounds__(NTHREADS) void k_xstage(StageArgs<T> a) {
@@ -1094,7 +1085,10 @@ __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
   const Geom& g = a.g;
   const long long tile = blockIdx.x;
   const TileRef tr = tile_ref(g, tile);
-  load_tile(g, tile, a.src, buf, a.S);
+  // tiles hold g.spt species (strided axes may hold one, with the species
+  // index in the outer block)
+  const int S = g.spt;
+  load_tile(g, tile, a.src, buf, S);
   __syncthreads();
   const int ne = g.n * g.W;
   if (a.pre_divide_w) {
@@ -1104,11 +1098,11 @@ __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
       long long idx;
       if (!elem(g, tr, j, w, idx)) continue;
       const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
-      for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] /= wt;
+      for (int s = 0; s < S; ++s) buf[(s * g.n + j) * g.pitch + w] /= wt;
     }
     __syncthreads();
   }
-  XFT<T>{&g, a.Mt}(buf, a.S);
+  XFT<T>{&g, a.Mt}(buf, S);
   if (a.post_multiply_w) {
     for (int e = threadIdx.x; e < ne; e += blockDim.x) {
       int j, w;
@@ -1116,11 +1110,11 @@ __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
       long long idx;
       if (!elem(g, tr, j, w, idx)) continue;
       const T wt = T(point_weight(idx, a.n0, a.n1, a.n2));
-      for (int s = 0; s < a.S; ++s) buf[(s * g.n + j) * g.pitch + w] *= wt;
+      for (int s = 0; s < S; ++s) buf[(s * g.n + j) * g.pitch + w] *= wt;
     }
     __syncthreads();
   }
-  store_tile(g, tile, buf, a.dst, a.S);
+  store_tile(g, tile, buf, a.dst, S);
 }
 
 // --------------------------------------------------------------------------

@@ -1,7 +1,8 @@
 // libsfrde: host plan, step drivers and the C ABI declared in include/sfrde.h.
 //
-// A plan holds, on the device: per-axis transform matrices (dtype, built in
-// FP64 on the host from the closed forms of Section 3.1), per-axis FP64
+// A plan holds, on the device: per-axis transform data (matrix-core
+// fragments, FFT twiddles or dense matrices, built in FP64 on the host from
+// the closed forms of Section 3.1), per-axis FP64
 // eigenvalue tables, the six coefficient tables of the Alg. 1 precompute
 // (computed in FP64 on the device, stored in dtype), and the workspace of the
 // step: one field buffer P that every kernel transforms in place, and the
@@ -9,7 +10,6 @@
 // adjoint buffers, a segment store for recomputed stage data and the
 // derivative tables.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -27,6 +27,7 @@
 
 #include "../../include/sfrde.h"
 #include "coef.h"
+#include "fft.h"
 #include "kernels.h"
 #include "mfma.h"
 #include "stability.h"
@@ -125,11 +126,12 @@ struct sfrde_plan_s {
   size_t lds[3] = {0, 0, 0};
   // matrix-core variant per axis (see mfma.h)
   bool use_m[3] = {false, false, false};
-  // axes too long for the matrix-core engine: transforms as library matrix
-  // products (rocBLAS) around pointwise-only tile kernels, through gtmp
-  bool use_g[3] = {false, false, false};
-  rocblas_handle blas = nullptr;
-  void* gtmp = nullptr;
+  // long periodic axes of 256, 512 or 1024 points: FFT tile kernels (fft.h)
+  bool use_f[3] = {false, false, false};
+  Geom geom_f[3]{};
+  size_t lds_f[3] = {0, 0, 0};
+  unsigned thr_f[3] = {0, 0, 0};
+  void* tw[3] = {nullptr, nullptr, nullptr};  // [N][2] cos, sin of 2 pi m / N
   Geom geom_m[3]{};
   size_t lds_m[3] = {0, 0, 0};
   unsigned grid_m[3] = {0, 0, 0};
@@ -421,8 +423,6 @@ double half_entry(const MfmaTables& t, int rb, int row16, int k) {
 }
 
 int setup_mfma_axis(sfrde_plan_s* p, int axis) {
-  const char* env = getenv("SFRDE_TRANSFORM");
-  if (env && strcmp(env, "dense") == 0) return SFRDE_OK;
   if (p->n[axis] < 2) return SFRDE_OK;  // padding axis of a 1D plan: dense kernels
   MfmaTables t = mfma_tables(p->bc, p->n[axis]);
   if (!t.ok) return SFRDE_OK;
@@ -479,7 +479,7 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   ax.fb_off = (int)tile_bytes;
   size_t lds = tile_bytes + std::max(fold_bytes, res_bytes);
   lds = std::max<size_t>(lds, (size_t)threads * sizeof(double));
-  if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: library products or dense kernels
+  if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: FFT or dense kernels
   p->lds_m[axis] = lds;
   // persistent grid: as many blocks as fit on the CUs at once
   const long long per_cu = 1;
@@ -521,6 +521,57 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   return SFRDE_OK;
 }
 
+// Long periodic axes of N = 256, 512 or 1024 points run the FFT tile kernels
+// (fft.h): x tiles hold 2 lines of every species (1 line for S > 2), strided
+// tiles 4 lines of one species, one wavefront per pair of lines.
+template <typename T>
+int setup_fft_axis(sfrde_plan_s* p, int axis) {
+  const long long n = p->n[axis];
+  if (p->use_m[axis] || p->bc != SFRDE_BC_PERIODIC ||
+      !(n == 256 || n == 512 || n == 1024))
+    return SFRDE_OK;
+  Geom& g = p->geom_f[axis];
+  g = p->geom[axis];
+  if (g.inner == 1) {
+    g.spt = p->S;
+    g.W = p->S <= 2 ? 2 : 1;
+    g.tpo = 1;
+    g.ntiles = (g.outer + g.W - 1) / g.W;
+  } else {
+    g.outer *= p->S;  // one species per tile: the species joins the outer index
+    g.spt = 1;
+    g.W = 4;
+    g.tpo = (g.inner + g.W - 1) / g.W;
+    g.ntiles = g.outer * g.tpo;
+  }
+  g.pitch = g.W | 1;  // odd: a line's elements fall in distinct LDS banks
+  g.wshift = 0;
+  while ((1 << g.wshift) < g.W) ++g.wshift;
+  g.fast = 0;
+  p->thr_f[axis] = 64u * (unsigned)fft_pairs(g.spt, g.W);
+  p->lds_f[axis] = fft_lds_bytes<T>(g.spt, g.n, g.W, g.pitch);
+  if (p->lds_f[axis] > 160 * 1024) return SFRDE_OK;  // dense kernels
+  const double pi = 3.14159265358979323846;
+  std::vector<T> tw((size_t)2 * n);
+  for (long long m = 0; m < n; ++m) {
+    tw[2 * m] = T(cos(2.0 * pi * double(m) / double(n)));
+    tw[2 * m + 1] = T(sin(2.0 * pi * double(m) / double(n)));
+  }
+  TRY(dev_alloc(p, &p->tw[axis], tw.size() * sizeof(T)));
+  HIPCHECK(hipMemcpy(p->tw[axis], tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
+  std::vector<const void*> fns = {
+      reinterpret_cast<const void*>(&k_xstage<T, FftXf>),
+      reinterpret_cast<const void*>(&k_zstage<T, FftXf>),
+      reinterpret_cast<const void*>(&k_xadj<T, FftXf>),
+      reinterpret_cast<const void*>(&k_zadj<T, FftXf>),
+      reinterpret_cast<const void*>(&k_single<T, FftXf>)};
+  for (const void* f : fns)
+    HIPCHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)p->lds_f[axis]));
+  p->use_f[axis] = true;
+  return SFRDE_OK;
+}
+
 template <typename T>
 int set_lds_attrs(size_t bytes) {
   std::vector<const void*> fns = {
@@ -557,8 +608,8 @@ int set_lds_attrs(size_t bytes) {
 template <typename T>
 StageArgs<T> stage_args(sfrde_plan_s* p, int axis, void* P) {
   StageArgs<T> a{};
-  a.g = p->use_m[axis] ? p->geom_m[axis] : p->geom[axis];
-  a.Mt = (const T*)p->Mt[axis];
+  a.g = p->use_m[axis] ? p->geom_m[axis] : p->use_f[axis] ? p->geom_f[axis] : p->geom[axis];
+  a.Mt = (const T*)(p->use_f[axis] ? p->tw[axis] : p->Mt[axis]);
   a.P = (T*)P;
   a.coef = (const T*)p->coef;
   a.ltab = (const T*)p->ltab;
@@ -602,50 +653,11 @@ bool use_fast(const sfrde_plan_s* p, int axis, std::initializer_list<const void*
   return true;
 }
 
-// Transform along `axis` of every field of the plan as a library matrix
-// product, src -> dst (not aliased). With M the axis matrix (column-major, as
-// the transposed table Mt is stored):
-//   x axis (contiguous lines):  dst (n x lines) = M src (n x lines)
-//   strided axis, per block o of n*inner points: dst_o (inner x n) = src_o (inner x n) M^T
-template <typename T>
-int gemm_axis(sfrde_plan_s* p, int axis, const T* src, T* dst) {
-  const long long n = p->n[axis];
-  long long inner = 1;
-  for (int a = 0; a < axis; ++a) inner *= p->n[a];
-  const long long elems = (long long)field_elems(p);
-  const long long cols = elems / n;  // lines (x) or outer blocks times inner
-  if (cols > INT32_MAX || n > INT32_MAX) return fail(SFRDE_EUNSUPPORTED, "field too large for rocBLAS");
-  const T one = T(1), zero = T(0);
-  const T* M = (const T*)p->Mt[axis];
-  rocblas_status st;
-  if (inner == 1) {
-    if constexpr (std::is_same<T, float>::value)
-      st = rocblas_sgemm(p->blas, rocblas_operation_none, rocblas_operation_none, (int)n, (int)cols,
-                         (int)n, &one, M, (int)n, src, (int)n, &zero, dst, (int)n);
-    else
-      st = rocblas_dgemm(p->blas, rocblas_operation_none, rocblas_operation_none, (int)n, (int)cols,
-                         (int)n, &one, M, (int)n, src, (int)n, &zero, dst, (int)n);
-  } else {
-    const long long batch = elems / (n * inner);
-    if (batch > INT32_MAX) return fail(SFRDE_EUNSUPPORTED, "field too large for rocBLAS");
-    if constexpr (std::is_same<T, float>::value)
-      st = rocblas_sgemm_strided_batched(p->blas, rocblas_operation_none, rocblas_operation_transpose,
-                                         (int)inner, (int)n, (int)n, &one, src, (int)inner, n * inner,
-                                         M, (int)n, 0, &zero, dst, (int)inner, n * inner, (int)batch);
-    else
-      st = rocblas_dgemm_strided_batched(p->blas, rocblas_operation_none, rocblas_operation_transpose,
-                                         (int)inner, (int)n, (int)n, &one, src, (int)inner, n * inner,
-                                         M, (int)n, 0, &zero, dst, (int)inner, n * inner, (int)batch);
-  }
-  if (st != rocblas_status_success) return fail(SFRDE_EDEVICE, "rocBLAS gemm failed (%d)", (int)st);
-  return SFRDE_OK;
-}
-
 template <typename T>
 int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre_div, int post_mul) {
   SingleArgs<T> a{};
-  a.g = p->use_m[axis] ? p->geom_m[axis] : p->geom[axis];
-  a.Mt = (const T*)p->Mt[axis];
+  a.g = p->use_m[axis] ? p->geom_m[axis] : p->use_f[axis] ? p->geom_f[axis] : p->geom[axis];
+  a.Mt = (const T*)(p->use_f[axis] ? p->tw[axis] : p->Mt[axis]);
   a.src = (const T*)src;
   a.dst = (T*)dst;
   a.S = p->S;
@@ -682,26 +694,9 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
       hipLaunchKernelGGL((k_single_m<T, XfZ<T>, false>), grid, block, lds, p->stream, a,
                          p->mfax[axis]);
     }
-  } else if (p->use_g[axis]) {
-    // library product through gtmp; the weights (or a copy) in a pointwise pass
-    T* tmp = (T*)p->gtmp;
-    a.g = p->geom[0];  // pointwise only: contiguous x-line tiles
-    const dim3 grid((unsigned)a.g.ntiles, p->B);
-    if (!a.pre_divide_w && !a.post_multiply_w && src != dst) {
-      TRY(gemm_axis<T>(p, axis, (const T*)src, (T*)dst));
-    } else if (a.pre_divide_w) {
-      SingleArgs<T> w = a;
-      w.dst = tmp;
-      w.post_multiply_w = 0;
-      hipLaunchKernelGGL((k_single<T, NoXf>), grid, dim3(NTHREADS), p->lds[0], p->stream, w);
-      HIPCHECK(hipGetLastError());
-      TRY(gemm_axis<T>(p, axis, tmp, (T*)dst));
-    } else {
-      TRY(gemm_axis<T>(p, axis, (const T*)src, tmp));
-      SingleArgs<T> w = a;
-      w.src = tmp;
-      hipLaunchKernelGGL((k_single<T, NoXf>), grid, dim3(NTHREADS), p->lds[0], p->stream, w);
-    }
+  } else if (p->use_f[axis]) {
+    hipLaunchKernelGGL((k_single<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B),
+                       dim3(p->thr_f[axis]), p->lds_f[axis], p->stream, a);
   } else
     hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
                        p->lds[axis], p->stream, a);
@@ -746,15 +741,9 @@ int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
     else
       hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
-  } else if (p->use_g[0]) {
-    T* tmp = (T*)p->gtmp;
-    TRY(gemm_axis<T>(p, 0, a.P, tmp));
-    StageArgs<T> b = a;
-    b.P = tmp;
-    hipLaunchKernelGGL((k_xstage<T, NoXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
-                       p->lds[0], p->stream, b);
-    HIPCHECK(hipGetLastError());
-    TRY(gemm_axis<T>(p, 0, tmp, a.P));
+  } else if (p->use_f[0]) {
+    hipLaunchKernelGGL((k_xstage<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[0]),
+                       p->lds_f[0], p->stream, a);
   } else
     hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
                        p->lds[0], p->stream, a);
@@ -801,17 +790,9 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat)
       launch_zstage_m<T>(fast, staged ? mode : -1, dim3(p->grid_m[ax], p->B), p->lds_m[ax],
                          p->stream, a, p->mfax[ax]);
     }
-  else if (p->use_g[ax]) {
-    // a spectral source is read by the pointwise pass itself
-    T* tmp = (T*)p->gtmp;
-    if (!src) TRY(gemm_axis<T>(p, ax, a.P, tmp));
-    StageArgs<T> b = a;
-    b.P = tmp;
-    b.g = p->geom[0];  // pointwise only: contiguous x-line tiles
-    hipLaunchKernelGGL((k_zstage<T, NoXf>), dim3((unsigned)b.g.ntiles, p->B), dim3(NTHREADS),
-                       p->lds[0], p->stream, b);
-    HIPCHECK(hipGetLastError());
-    TRY(gemm_axis<T>(p, ax, tmp, a.P));
+  else if (p->use_f[ax]) {
+    hipLaunchKernelGGL((k_zstage<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[ax]),
+                       p->lds_f[ax], p->stream, a);
   } else
     hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
                        p->lds[ax], p->stream, a);
@@ -970,15 +951,9 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
     else
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
-  } else if (p->use_g[0]) {
-    T* tmp = (T*)p->gtmp;
-    TRY(gemm_axis<T>(p, 0, a.P, tmp));
-    StageArgs<T> b = a;
-    b.P = tmp;
-    hipLaunchKernelGGL((k_xadj<T, NoXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
-                       p->lds[0], p->stream, b);
-    HIPCHECK(hipGetLastError());
-    TRY(gemm_axis<T>(p, 0, tmp, a.P));
+  } else if (p->use_f[0]) {
+    hipLaunchKernelGGL((k_xadj<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[0]),
+                       p->lds_f[0], p->stream, a);
   } else
     hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
                        p->lds[0], p->stream, a);
@@ -1025,16 +1000,9 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
     else
       hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, false>), grid, block, p->lds_m[ax], p->stream, a,
                          p->mfax[ax]);
-  } else if (p->use_g[ax]) {
-    T* tmp = (T*)p->gtmp;
-    TRY(gemm_axis<T>(p, ax, a.P, tmp));
-    StageArgs<T> b = a;
-    b.P = tmp;
-    b.g = p->geom[0];  // pointwise only: contiguous x-line tiles
-    hipLaunchKernelGGL((k_zadj<T, NoXf>), dim3((unsigned)b.g.ntiles, p->B), dim3(NTHREADS),
-                       p->lds[0], p->stream, b);
-    HIPCHECK(hipGetLastError());
-    TRY(gemm_axis<T>(p, ax, tmp, a.P));
+  } else if (p->use_f[ax]) {
+    hipLaunchKernelGGL((k_zadj<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[ax]),
+                       p->lds_f[ax], p->stream, a);
   } else
     hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
                        p->lds[ax], p->stream, a);
@@ -1098,7 +1066,8 @@ int coef_tables(sfrde_plan_s* p, int deriv, void* out) {
 
 // Blocks of the adjoint X kernel (each owns one accumulator per parameter).
 long long rp_blocks(const sfrde_plan_s* p) {
-  return p->use_m[0] ? (long long)p->grid_m[0] : p->geom[0].ntiles;
+  return p->use_m[0] ? (long long)p->grid_m[0]
+                      : p->use_f[0] ? p->geom_f[0].ntiles : p->geom[0].ntiles;
 }
 
 // Bytes of the backward buffers (what ensure_backward_buffers allocates),
@@ -1298,14 +1267,13 @@ void destroy_plan(sfrde_plan_s* p) {
   void** ptrs[] = {&p->Mt[0], &p->Mt[1], &p->Mt[2], (void**)&p->lam[0], (void**)&p->lam[1],
                    (void**)&p->lam[2], &p->coef, &p->dcoef, &p->ltab, &p->P, &p->uhat, &p->ctil, &p->acc,
                    &p->Pa, &p->zh, &p->aacc, &p->ahat, &p->gu, (void**)&p->G, &p->seg,
-                   (void**)&p->rp_acc, (void**)&p->thp, (void**)&p->red, (void**)&p->flag, (void**)&p->rxm, &p->gtmp, &p->mf_A[0],
+                   (void**)&p->rp_acc, (void**)&p->thp, (void**)&p->red, (void**)&p->flag, (void**)&p->rxm, &p->tw[0], &p->tw[1], &p->tw[2], &p->mf_A[0],
                    &p->mf_A[1], &p->mf_A[2]};
   for (void** q : ptrs) {
     if (*q) (void)hipFree(*q);
     *q = nullptr;
   }
   if (p->h_flag) (void)hipHostFree(p->h_flag);
-  if (p->blas) (void)rocblas_destroy_handle(p->blas);
   for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
   delete p;
 }
@@ -1372,10 +1340,6 @@ int build_plan(sfrde_plan_s* p) {
   p->device = dev;
   TRY(scratch_address(dev, &p->scratch));
   for (int a = 0; a < p->ndim; ++a) {
-    if (p->dtype == SFRDE_F32)
-      TRY(upload_matrix<float>(p, a));
-    else
-      TRY(upload_matrix<double>(p, a));
     std::vector<double> lam(p->n[a]);
     for (long long k = 0; k < p->n[a]; ++k)
       lam[k] = p->n[a] == 1 ? 0.0 : axis_eigenvalue(p->bc, p->n[a], p->h[a], k);
@@ -1387,36 +1351,31 @@ int build_plan(sfrde_plan_s* p) {
   for (int a = 0; a < p->ndim; ++a)
     make_geom(p, a, std::max<long long>(1, (2LL * p->n_cu + p->B - 1) / p->B));
   for (int a = 0; a < p->ndim; ++a) TRY(setup_mfma_axis(p, a));
-  {
-    // Axes the matrix-core engine does not take (periodic n >= 256, others
-    // n > 256): library matrix products (SFRDE_TRANSFORM=dense keeps the
-    // LDS kernels). The one-point padding axis of 1D plans stays dense.
-    const char* env = getenv("SFRDE_TRANSFORM");
-    const bool dense_only = env && strcmp(env, "dense") == 0;
-    bool any = false;
-    for (int a = 0; a < p->ndim; ++a) {
-      p->use_g[a] = !dense_only && !p->use_m[a] && p->n[a] >= 64;
-      any = any || p->use_g[a];
-    }
-    if (any) {
-      if (rocblas_create_handle(&p->blas) != rocblas_status_success)
-        return fail(SFRDE_EDEVICE, "rocblas_create_handle failed");
-      if (rocblas_set_stream(p->blas, p->stream) != rocblas_status_success)
-        return fail(SFRDE_EDEVICE, "rocblas_set_stream failed");
-      TRY(dev_alloc(p, &p->gtmp, field_bytes(p)));
+  // Long periodic axes of 256, 512 or 1024 points: FFT kernels. Any other
+  // axis the matrix-core engine does not take (n > 256, other periodic
+  // n >= 256, the one-point padding axis of 1D plans) runs the dense LDS
+  // kernels with the axis matrix.
+  for (int a = 0; a < p->ndim; ++a) {
+    if (p->dtype == SFRDE_F32)
+      TRY(setup_fft_axis<float>(p, a));
+    else
+      TRY(setup_fft_axis<double>(p, a));
+    if (!p->use_m[a] && !p->use_f[a]) {
+      if (p->dtype == SFRDE_F32)
+        TRY(upload_matrix<float>(p, a));
+      else
+        TRY(upload_matrix<double>(p, a));
     }
   }
   {
     // FP32 P13 plans whose last axis runs the vector Z kernels form L there
     // from the eigenvalue tables (kept in LDS as floats) instead of reading
-    // an L table (SFRDE_COEF=table keeps the table).
+    // an L table.
     const int za = p->ndim - 1;
-    const char* cenv = getenv("SFRDE_COEF");
-    const bool table = cenv && strcmp(cenv, "table") == 0;
     long long nsum = 0;
     for (int a = 0; a < p->ndim; ++a) nsum += p->n[a];
     const size_t extra = (size_t)nsum * sizeof(float);
-    if (p->dtype == SFRDE_F32 && p->scheme == SFRDE_SCHEME_P13 && !table && p->B == 1 &&
+    if (p->dtype == SFRDE_F32 && p->scheme == SFRDE_SCHEME_P13 && p->B == 1 &&
         p->use_m[za] &&
         p->geom_m[za].fast && p->n[0] % 4 == 0 && p->lds_m[za] + extra <= 160 * 1024) {
       p->lfly = true;
@@ -1637,10 +1596,6 @@ int sfrde_backward_noalloc(sfrde_plan_t p, const void* ckpt, int64_t nsteps,
   if (!p) return fail(SFRDE_EINVAL, "plan is NULL");
   if (!ckpt || !grad_uT) return fail(SFRDE_EINVAL, "ckpt and grad_uT must not be NULL");
   if (nsteps < 1 || ckpt_every < 1) return fail(SFRDE_EINVAL, "nsteps, ckpt_every must be >= 1");
-  for (int a = 0; a < p->ndim; ++a)
-    if (p->use_g[a])
-      return fail(SFRDE_EUNSUPPORTED,
-                  "the allocation-free backward does not run plans with library-product axes");
   if (!p->scratch) return fail(SFRDE_EDEVICE, "the plan has no scratch address");
   TRY(check_header(p, ckpt, nsteps, ckpt_every));
   if (p->rxn.kind >= RXN_HUXLEY_MMS && (grad_kappa || grad_alpha))

@@ -11,7 +11,7 @@ import workloads as W
 from oracle import problem
 from paper_2003_13569_amd.torch_api import Plan
 from tests.gpu_util import TD
-from tests.test_gpu_parity import CASES, DENSE_CASES, VEC_CASES
+from tests.test_gpu_parity import CASES, DENSE_CASES, FFT_CASES, VEC_CASES
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,8 @@ def _batch_plan(members, dtype):
                 batch=len(members))
 
 
-BATCH_CASES = [CASES[2], CASES[3], CASES[6], DENSE_CASES[1]]  # ..., a library-product axis
+# ..., a dense-kernel axis, an FFT axis
+BATCH_CASES = [CASES[2], CASES[3], CASES[6], DENSE_CASES[1], FFT_CASES[0]]
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
@@ -84,11 +85,11 @@ def test_batch_adjoint_matches_oracle_per_member():
     S, npar = wl.nspecies, len(wl.params)
     for b, m in enumerate(members):
         ref = problem.gradients(m, u0[b], M, wbar[b])
-        assert problem.rel_err(g_u0[b], ref["u0"]) <= 1e-9
+        assert problem.rel_err(g_u0[b], ref["u0"]) <= 1e-10
         for key, got in (("kappa", gk[b * S:(b + 1) * S]), ("alpha", ga[b * S:(b + 1) * S]),
                          ("params", gp[b * npar:(b + 1) * npar])):
             r = ref[key]
-            assert np.max(np.abs(np.array(got) - r)) <= 1e-9 * max(np.max(np.abs(r)), 1e-300), \
+            assert np.max(np.abs(np.array(got) - r)) <= 1e-10 * max(np.max(np.abs(r)), 1e-300), \
                 (b, key, got, r)
     p.close()
 

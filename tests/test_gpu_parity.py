@@ -91,8 +91,9 @@ def test_fp32_vector_paths_match_oracle(wl, scheme):
     assert problem.rel_err(got, ref) <= 2e-5
 
 
-# Axes whose folded length exceeds the matrix-core limit (n > 256, periodic
-# n >= 256) take the dense LDS kernels, with tiles narrowed to fill the device.
+# Axes the matrix-core engine and the FFT kernels do not take (n > 256, and
+# periodic n >= 256 that is not 256, 512 or 1024) run the dense LDS kernels,
+# with tiles narrowed to fill the device.
 DENSE_CASES = [
     _wl("gs2d-per-dense", "periodic", (24, 300), "gray_scott", GS, (1.7, 1.7), (2e-3, 1e-3), 1.0,
         "gs_square", (-1.0, 1.0)),
@@ -111,15 +112,32 @@ def test_dense_axes_match_oracle(wl, dtype, tol, scheme):
     assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
 
 
-def test_lds_dense_kernels_match_oracle(monkeypatch):
-    # SFRDE_TRANSFORM=dense: the long axes take the LDS dense kernels instead of
-    # library matrix products.
-    monkeypatch.setenv("SFRDE_TRANSFORM", "dense")
-    for wl in DENSE_CASES:
-        u0 = W.initial_fields(wl)
-        ref = problem.run(wl, u0, 3)
-        assert problem.rel_err(run(wl, u0, 3, "f64"), ref) <= 1e-10
-        assert problem.rel_err(run(wl, u0, 3, "f32"), ref) <= 2e-5
+# Long periodic axes of 256, 512 and 1024 points take the FFT kernels: on x
+# (every species per tile), on the middle and last axes (one species per
+# tile), with ragged partners, and with an odd line count per tile (three
+# species, one x line per tile).
+FFT_CASES = [
+    _wl("gs2d-per-fft-x", "periodic", (24, 512), "gray_scott", GS, (1.7, 1.5), (2e-3, 1e-3), 1.0,
+        "gs_square", (-1.0, 1.0)),
+    _wl("gs2d-per-fft-y", "periodic", (256, 40), "gray_scott", GS, (1.7, 1.9), (2e-3, 1e-3), 1.0,
+        "gs_square", (-1.0, 1.0)),
+    _wl("sch3d-per-fft-mid", "periodic", (6, 256, 10), "schnakenberg", SCH, (1.8, 1.6),
+        (0.05, 1.0), 0.01, "schnak_noise", (0.0, 1.0)),
+    _wl("sch3d-per-fft-xz", "periodic", (512, 3, 256), "schnakenberg", SCH, (1.5, 1.2),
+        (0.05, 1.0), 0.01, "schnak_noise", (0.0, 1.0)),
+    _wl("lin3-per-fft-x", "periodic", (5, 512), "linear", (-0.5, 0.25, -1.0), (1.6, 1.8, 1.2),
+        (1e-3, 2e-3, 5e-4), 0.5, "normal", (0.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("scheme", ["p13", "exp"])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+@pytest.mark.parametrize("wl", FFT_CASES, ids=[c.name for c in FFT_CASES])
+def test_fft_axes_match_oracle(wl, dtype, tol, scheme):
+    wl = wl.replace(scheme=scheme)
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 5)
+    assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
 
 
 # The benchmark configurations at their full sizes, a few steps.
@@ -178,8 +196,8 @@ def test_fp32_full_horizon_matches_fp64_gpu(wl, alpha, nsteps):
 
 
 # The largest axes a plan accepts (1024 unknowns), on each kind of axis:
-# contiguous x, strided middle and strided last (library products), ragged
-# partners on the other axes.
+# contiguous x, strided middle and strided last (dense kernels; periodic x on
+# the FFT kernels), ragged partners on the other axes.
 MAX_CASES = [
     _wl("max2d-neu", "neumann", (1024, 700), "gray_scott", GS, (1.7, 1.5), (2e-3, 1e-3), 0.5,
         "gs_square", (-1.0, 1.0)),
@@ -359,10 +377,10 @@ def test_one_dimensional_adjoint_matches_oracle(wl):
     gk, ga, gp = p.backward(ck, 5, 2, torch.tensor(wbar, device="cuda"), 0.0, g0)
     torch.cuda.synchronize()
     p.close()
-    assert problem.rel_err(g0.cpu().numpy(), ref["u0"]) <= 1e-9
+    assert problem.rel_err(g0.cpu().numpy(), ref["u0"]) <= 1e-10
     for key, got in (("kappa", gk), ("alpha", ga), ("params", gp)):
         r = ref[key]
-        assert np.max(np.abs(np.array(got) - r)) <= 1e-9 * max(np.max(np.abs(r)), 1e-300), key
+        assert np.max(np.abs(np.array(got) - r)) <= 1e-10 * max(np.max(np.abs(r)), 1e-300), key
 
 
 def test_single_steps_match_integrate():
