@@ -771,14 +771,16 @@ void launch_zstage_m(bool fast, int mode, dim3 grid, size_t lds, hipStream_t st,
   hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, -1, false>), grid, block, lds, st, a, ax);
 }
 
+// uhat: the spectral state this stage reads (stages 0, 1) or writes (stage
+// 3); NULL: the plan's own.
 template <typename T>
-int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_uhat, T* st_fhat) {
+int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_fhat, T* uhat = nullptr) {
   const int ax = p->ndim - 1;
   StageArgs<T> a = stage_args<T>(p, ax, p->P);
   a.mode = mode;
   a.src = (const T*)src;
-  a.st_uhat = st_uhat;
   a.st_fhat = st_fhat;
+  if (uhat) a.uhat = uhat;
   const long long pk = prof_start(p, KC_Z);
   if (p->use_m[ax])
     {
@@ -814,25 +816,33 @@ template <typename T>
 int prologue_physical(sfrde_plan_s* p, const void* state) {
   TRY(launch_single<T>(p, 0, state, p->P, 0, 0));
   TRY(ypass<T>(p, p->P));
-  TRY(launch_z<T>(p, MODE_INIT, nullptr, nullptr, nullptr));
+  TRY(launch_z<T>(p, MODE_INIT, nullptr, nullptr));
   return ypass<T>(p, p->P);
 }
 
+// P from a stored spectral state (a checkpoint slot), read in place; the
+// plan's u_hat is set from it when `set_uhat` (a forward continuation).
 template <typename T>
-int prologue_spectral(sfrde_plan_s* p, const void* spec) {
-  HIPCHECK(hipMemcpyAsync(p->uhat, spec, field_bytes(p), hipMemcpyDeviceToDevice, p->stream));
-  TRY(launch_z<T>(p, MODE_RESTORE, p->uhat, nullptr, nullptr));
+int prologue_spectral(sfrde_plan_s* p, const void* spec, bool set_uhat = true) {
+  if (set_uhat)
+    HIPCHECK(hipMemcpyAsync(p->uhat, spec, field_bytes(p), hipMemcpyDeviceToDevice, p->stream));
+  TRY(launch_z<T>(p, MODE_RESTORE, set_uhat ? p->uhat : spec, nullptr));
   return ypass<T>(p, p->P);
 }
 
 // One step of eq. ETDRK4P13 from t (four stages); stores stage data if asked.
+// uh_in / uh_out: where the step reads u_hat and writes the next one (NULL:
+// the plan's u_hat); the recompute of a segment reads and writes the
+// segment store's slots, so that u_hat of every step is stored without a
+// copy.
 template <typename T>
-int run_step(sfrde_plan_s* p, double t, const StepStore<T>* st) {
+int run_step(sfrde_plan_s* p, double t, const StepStore<T>* st, T* uh_in = nullptr,
+             T* uh_out = nullptr) {
   const double off[4] = {0.0, 0.5 * p->dt, 0.5 * p->dt, p->dt};
   for (int j = 0; j < 4; ++j) {
     TRY(launch_x<T>(p, j, t + off[j], st ? st->phys : nullptr));
     TRY(ypass<T>(p, p->P));
-    TRY(launch_z<T>(p, j, nullptr, st ? st->uhat : nullptr, st ? st->fhat : nullptr));
+    TRY(launch_z<T>(p, j, nullptr, st ? st->fhat : nullptr, j == 3 ? uh_out : uh_in));
     TRY(ypass<T>(p, p->P));
   }
   return SFRDE_OK;
@@ -1189,13 +1199,22 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
     const long long nseg = (nsteps + K - 1) / K;
     for (long long sgi = nseg - 1; sgi >= 0 && rc == SFRDE_OK; --sgi) {
       const long long k0 = sgi * K, k1 = std::min(nsteps, k0 + K);
-      if ((rc = prologue_spectral<T>(p, ckpt_slot(p, (void*)ckpt, sgi)))) break;
-      for (long long k = k0; k < k1 && rc == SFRDE_OK; ++k) {
+      // the segment's u_hat of step k sits in store slot k - k0, that of its
+      // first step in the checkpoint itself (read in place)
+      T* ck = reinterpret_cast<T*>(ckpt_slot(p, (void*)ckpt, sgi));
+      auto store_at = [&](long long k) {
         StepStore<T> st = step_store<T>(p, k - k0);
-        rc = run_step<T>(p, t0 + double(k) * p->dt, &st);
+        if (k == k0) st.uhat = ck;
+        return st;
+      };
+      if ((rc = prologue_spectral<T>(p, ck, false))) break;
+      for (long long k = k0; k < k1 && rc == SFRDE_OK; ++k) {
+        StepStore<T> st = store_at(k);
+        T* out = k + 1 < k1 ? store_at(k + 1).uhat : (T*)p->uhat;
+        rc = run_step<T>(p, t0 + double(k) * p->dt, &st, st.uhat, out);
       }
       for (long long k = k1 - 1; k >= k0 && rc == SFRDE_OK; --k) {
-        StepStore<T> st = step_store<T>(p, k - k0);
+        StepStore<T> st = store_at(k);
         rc = adjoint_step<T>(p, st, k == 0);
       }
     }
