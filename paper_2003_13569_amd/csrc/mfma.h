@@ -822,8 +822,9 @@ __device__ __forceinline__ void tile_store(const Geom& g, long long tile, const 
     store_tile_fast(g, tile, buf, dst, g.spt);
 }
 
-// Arrays a forward stage reads for one strided FP32 tile of n = 256 rows,
-// loaded one tile ahead in the thread layout of TileIO<float, 32>:
+// Arrays a forward stage reads for one strided FP32 tile of n = 64, 128 or
+// 256 rows, loaded one tile ahead in the thread layout of TileIO<float, 32>
+// (straight-line loads: row blocks past n load block 0 again, unused):
 //   r1, r2 = stage 0: u_hat, -;  1: u_hat, acc;  2: acc, c_tilde;  3: acc, -
 // and L when the plan reads an L table.
 template <int MODE>
@@ -838,7 +839,7 @@ struct StageLoads {
     const float* p2 = MODE == 1 ? a.acc : a.ctil;
 #pragma unroll
     for (int k = 0; k < IO::MAXK; ++k) {
-      const long long i = i0 + k * IO::RSTEP * inner;
+      const long long i = i0 + (64 * k < a.g.n ? k : 0) * IO::RSTEP * inner;
       if (!a.lfly) L[k] = *reinterpret_cast<const float4*>(a.ltab + i);
       r1[k] = *reinterpret_cast<const float4*>(p1 + i);
       if (MODE == 1 || MODE == 2) r2[k] = *reinterpret_cast<const float4*>(p2 + i);
@@ -846,8 +847,8 @@ struct StageLoads {
   }
 };
 
-// Stage combine of one 256-row strided FP32 tile from preloaded arrays (same
-// arithmetic as combine_vec). With a.lfly, L = kt_s Lambda^ha_s is formed
+// Stage combine of one strided FP32 tile (64, 128 or 256 rows) from
+// preloaded arrays (same arithmetic as combine_vec). With a.lfly, L = kt_s Lambda^ha_s is formed
 // from the eigenvalue tables in LDS ([n0] x, [n1] y, then the transformed
 // last axis); the last axis has one outer block per species.
 template <int MODE>
@@ -881,6 +882,7 @@ __device__ __forceinline__ void combine_pre(const StageArgs<float>& a, float* bu
   }
 #pragma unroll
   for (int k = 0; k < IO::MAXK; ++k) {
+    if (64 * k >= g.n) break;
     const long long i = i0 + k * IO::RSTEP * inner;
     float* cell = buf + (r0 + IO::RSTEP * k) * IO::P + w4;
     const float4 fh = make_float4(cell[0], cell[1], cell[2], cell[3]);
@@ -1403,8 +1405,8 @@ struct TileRun {
   }
 };
 
-// MODE >= 0 (FAST FP32 plans whose last axis has 256 points, forward
-// stages): the stage arrays of the next tile are loaded while this one is
+// MODE >= 0 (FAST FP32 plans, forward stages; last axes of 64, 128, 192 or
+// 256 points): the stage arrays of the next tile are loaded while this one is
 // computed, each block taking a run of tiles. MODE < 0 takes a.mode at run
 // time.
 template <typename T, class XF, int MODE, bool FAST>

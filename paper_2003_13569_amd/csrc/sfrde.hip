@@ -785,10 +785,10 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_fhat, T* uhat = n
   if (p->use_m[ax])
     {
       const bool fast = use_fast<T>(p, ax, {p->P, src});
-      // the per-stage kernels: forward stages of 256-point last axes, L formed
-      // in the kernel or read from the table
-      const bool staged = fast && p->n[ax] == 256 && mode >= 0 && mode <= 3 && !src &&
-                          (p->lfly || p->ltab);
+      // the per-stage kernels: forward stages (the vector layout holds last
+      // axes of 64 to 256 points in steps of 64), L formed in the kernel or
+      // read from the table
+      const bool staged = fast && mode >= 0 && mode <= 3 && !src && (p->lfly || p->ltab);
       launch_zstage_m<T>(fast, staged ? mode : -1, dim3(p->grid_m[ax], p->B), p->lds_m[ax],
                          p->stream, a, p->mfax[ax]);
     }

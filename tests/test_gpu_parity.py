@@ -49,7 +49,7 @@ IDS = [c.name for c in CASES]
 
 # Shapes that take the FP32 vector tile paths: x tiles of 32 lines with
 # n_x in {64, 128, 256}; strided axes with 32-lane tiles and 64 | n; the
-# per-stage Z kernels (last axis of 256 points, L formed in the kernel).
+# per-stage Z kernels (last axes of 64 to 256 points, L formed in the kernel).
 VEC_CASES = [
     _wl("sch3d-neu-vec", "neumann", (256, 32, 64), "schnakenberg", SCH, (1.5, 1.2), (0.05, 1.0),
         0.005, "schnak_noise", (0.0, 1.0)),
@@ -59,6 +59,11 @@ VEC_CASES = [
         0.05, "gm_noise", (0.0, 2.0)),
     _wl("gs3d-per-vec", "periodic", (64, 64, 64), "gray_scott", GS, (1.7, 1.9), (2e-3, 1e-3), 0.5,
         "gs_square", (-1.0, 1.0)),
+    # per-stage Z kernels on last axes of 128 and 192 points
+    _wl("sch3d-dir-vec128", "dirichlet", (128, 32, 64), "schnakenberg", SCH, (1.8, 1.6),
+        (0.05, 1.0), 0.01, "schnak_noise", (0.0, 1.0)),
+    _wl("sch3d-neu-vec192", "neumann", (192, 32, 64), "schnakenberg", SCH, (1.5, 1.2),
+        (0.05, 1.0), 0.005, "schnak_noise", (0.0, 1.0)),
 ]
 VEC_IDS = [c.name for c in VEC_CASES]
 
