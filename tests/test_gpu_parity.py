@@ -346,6 +346,18 @@ def test_nonfinite_reaction_is_reported():
     p.close()
 
 
+def test_nonfinite_reaction_is_reported_after_many_steps():
+    wl = CASES[2]
+    u0 = W.initial_fields(wl)
+    u0[1] = 0.0
+    p = plan_for(wl, "f64")
+    u = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    with pytest.raises(C.SfrdeError) as ei:
+        p.integrate(u, 20)
+    assert ei.value.code == C.ENONFINITE
+    p.close()
+
+
 def test_null_state_is_rejected_on_a_live_plan():
     p = plan_for(CASES[0], "f64")
     assert C.lib().sfrde_integrate(p.handle, None, 1, 0.0, 0, None) == C.EINVAL
