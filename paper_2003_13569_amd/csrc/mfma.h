@@ -474,10 +474,20 @@ struct MfmaXfF64 {
       if (wave < ax->RB) {
         const int half = wave < ax->RBe ? 0 : 1;
         const double* bp = fb + (half * W + lane % 16) * ax->fb_pitch + lane / 16;
+        // four independent accumulators over ks mod 4 (the folded length is a
+        // multiple of 32, so KS is a multiple of 8): four MFMA chains in flight
+        // instead of one dependent chain of KS products
+        f64x4 acc1 = f64x4{0.0, 0.0, 0.0, 0.0}, acc2 = acc1, acc3 = acc1;
 #pragma unroll
-        for (int ks = 0; ks < MF_KSMAX_F64; ++ks) {
-          if (ks < KS) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks], bp[4 * ks], acc, 0, 0, 0);
+        for (int ks = 0; ks < MF_KSMAX_F64; ks += 4) {
+          if (ks < KS) {
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks], bp[4 * ks], acc, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks + 1], bp[4 * ks + 4], acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks + 2], bp[4 * ks + 8], acc2, 0, 0, 0);
+            acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks + 3], bp[4 * ks + 12], acc3, 0, 0, 0);
+          }
         }
+        acc = (acc + acc1) + (acc2 + acc3);
       }
       // f64 16x16x4 result layout: lane l, register r holds row 4r + l/16, column l%16
       if (ax->direct) {
@@ -1294,6 +1304,21 @@ __device__ __forceinline__ void combine_tile(const StageArgs<T>& a, T* buf, long
   pw_combine_fast(a, buf, tile);
 }
 
+// Forward combine of one stage known at compile time (the FP64 per-stage Z
+// kernels): vectors on full strided tiles, else the generic pass.
+template <typename T, int MODE>
+__device__ __forceinline__ void combine_mode(const StageArgs<T>& a, T* buf, long long tile) {
+  const TileRef tr = tile_ref(a.g, tile);
+  if (a.g.inner == 1 || !tile_vectorizable<T>(a.g, tr, a.uhat)) {
+    pw_combine(a, buf, tile);
+    return;
+  }
+  if (a.ltab)
+    combine_vec<T, MODE, true>(a, buf, tr);
+  else
+    combine_vec<T, MODE, false>(a, buf, tr);
+}
+
 // Inputs of the fold of an x tile (two species, 32 lines, n in {64, 128,
 // 256}, DCT-I / DST-I), read straight into registers: thread t takes line
 // (t/16) mod 32, entries i0 .. i0+7 and n-8-i0 .. n-1-i0 with i0 = 8 (t%16)
@@ -1459,7 +1484,10 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
     for (long long tile = run.t0; tile < run.t1; ++tile) {
       const long long next = run.next(tile);
       if (!a.src) xf(buf, S);
-      combine_tile<T, XF::W, FAST>(a, buf, tile);
+      if constexpr (MODE >= 0 && MODE <= 3 && !std::is_same<T, float>::value)
+        combine_mode<T, MODE>(a, buf, tile);
+      else
+        combine_tile<T, XF::W, FAST>(a, buf, tile);
       __syncthreads();
       pipe.issue(a.g, next, src);
       xf(buf, S);

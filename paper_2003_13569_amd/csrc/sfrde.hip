@@ -577,6 +577,10 @@ int set_lds_attrs(size_t bytes) {
   std::vector<const void*> fns = {
       reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>, false>),
       reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, -1, false>),
+      reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 0, false>),
+      reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 1, false>),
+      reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 2, false>),
+      reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 3, false>),
       reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, false>),
       reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, false>),
       reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, false>),
@@ -768,6 +772,15 @@ void launch_zstage_m(bool fast, int mode, dim3 grid, size_t lds, hipStream_t st,
       }
     }
   }
+  if constexpr (!std::is_same<T, float>::value) {
+    switch (mode) {
+      case 0: hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, 0, false>), grid, block, lds, st, a, ax); return;
+      case 1: hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, 1, false>), grid, block, lds, st, a, ax); return;
+      case 2: hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, 2, false>), grid, block, lds, st, a, ax); return;
+      case 3: hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, 3, false>), grid, block, lds, st, a, ax); return;
+      default: break;
+    }
+  }
   hipLaunchKernelGGL((k_zstage_m<T, XfZ<T>, -1, false>), grid, block, lds, st, a, ax);
 }
 
@@ -789,8 +802,8 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_fhat, T* uhat = n
       // axes of 64 to 256 points in steps of 64), L formed in the kernel or
       // read from the table
       const bool staged = fast && mode >= 0 && mode <= 3 && !src && (p->lfly || p->ltab);
-      launch_zstage_m<T>(fast, staged ? mode : -1, dim3(p->grid_m[ax], p->B), p->lds_m[ax],
-                         p->stream, a, p->mfax[ax]);
+      launch_zstage_m<T>(fast, staged || (!fast && !src && mode >= 0 && mode <= 3) ? mode : -1,
+                         dim3(p->grid_m[ax], p->B), p->lds_m[ax], p->stream, a, p->mfax[ax]);
     }
   else if (p->use_f[ax]) {
     hipLaunchKernelGGL((k_zstage<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[ax]),
