@@ -81,43 +81,49 @@ __device__ __forceinline__ void dft_r(T (&vr)[R], T (&vi)[R]) {
 
 // One Stockham stage of radix R and span NS on the wavefront's buffer
 // (xr, xi) of N points. Block-wide barriers: every wavefront of the block
-// runs the same stages.
+// runs the same stages; wavefronts without a line pair (`on` false) only
+// take part in the barriers.
 template <typename T, int N, int R, int NS>
-__device__ __forceinline__ void fft_stage(T* xr, T* xi, const T* __restrict__ tw, int lane) {
+__device__ __forceinline__ void fft_stage(T* xr, T* xi, const T* __restrict__ tw, int lane,
+                                          bool on) {
   constexpr int NB = N / R;  // butterflies
   constexpr int B = NB / 64;  // per lane
   static_assert(B >= 1 && NB % 64 == 0, "at least one butterfly per lane");
   T vr[B][R], vi[B][R];
+  if (on) {
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const int j = lane + 64 * b;
+    for (int b = 0; b < B; ++b) {
+      const int j = lane + 64 * b;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      vr[b][r] = xr[j + r * NB];
-      vi[b][r] = xi[j + r * NB];
+      for (int r = 0; r < R; ++r) {
+        vr[b][r] = xr[j + r * NB];
+        vi[b][r] = xi[j + r * NB];
+      }
     }
   }
   __syncthreads();
+  if (on) {
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const int j = lane + 64 * b;
-    const int k = j & (NS - 1);
-    if constexpr (NS > 1) {
+    for (int b = 0; b < B; ++b) {
+      const int j = lane + 64 * b;
+      const int k = j & (NS - 1);
+      if constexpr (NS > 1) {
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        const int m = r * k * (N / (NS * R));  // < N
-        const T c = tw[2 * m], s = tw[2 * m + 1];
-        const T ar = vr[b][r], ai = vi[b][r];
-        vr[b][r] = ar * c + ai * s;  // times e^{-i theta}
-        vi[b][r] = ai * c - ar * s;
+        for (int r = 1; r < R; ++r) {
+          const int m = r * k * (N / (NS * R));  // < N
+          const T c = tw[2 * m], s = tw[2 * m + 1];
+          const T ar = vr[b][r], ai = vi[b][r];
+          vr[b][r] = ar * c + ai * s;  // times e^{-i theta}
+          vi[b][r] = ai * c - ar * s;
+        }
       }
-    }
-    dft_r<T, R>(vr[b], vi[b]);
-    const int base = (j - k) * R + k;
+      dft_r<T, R>(vr[b], vi[b]);
+      const int base = (j - k) * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      xr[base + r * NS] = vr[b][r];
-      xi[base + r * NS] = vi[b][r];
+      for (int r = 0; r < R; ++r) {
+        xr[base + r * NS] = vr[b][r];
+        xi[base + r * NS] = vi[b][r];
+      }
     }
   }
   __syncthreads();
@@ -125,28 +131,32 @@ __device__ __forceinline__ void fft_stage(T* xr, T* xi, const T* __restrict__ tw
 
 // Complex DFT of the wavefront's buffer, natural order in and out.
 template <typename T, int N>
-__device__ __forceinline__ void fft_wave(T* xr, T* xi, const T* __restrict__ tw, int lane) {
+__device__ __forceinline__ void fft_wave(T* xr, T* xi, const T* __restrict__ tw, int lane,
+                                         bool on) {
   if constexpr (N == 256) {
-    fft_stage<T, N, 4, 1>(xr, xi, tw, lane);
-    fft_stage<T, N, 4, 4>(xr, xi, tw, lane);
-    fft_stage<T, N, 4, 16>(xr, xi, tw, lane);
-    fft_stage<T, N, 4, 64>(xr, xi, tw, lane);
+    fft_stage<T, N, 4, 1>(xr, xi, tw, lane, on);
+    fft_stage<T, N, 4, 4>(xr, xi, tw, lane, on);
+    fft_stage<T, N, 4, 16>(xr, xi, tw, lane, on);
+    fft_stage<T, N, 4, 64>(xr, xi, tw, lane, on);
   } else if constexpr (N == 512) {
-    fft_stage<T, N, 8, 1>(xr, xi, tw, lane);
-    fft_stage<T, N, 8, 8>(xr, xi, tw, lane);
-    fft_stage<T, N, 8, 64>(xr, xi, tw, lane);
+    fft_stage<T, N, 8, 1>(xr, xi, tw, lane, on);
+    fft_stage<T, N, 8, 8>(xr, xi, tw, lane, on);
+    fft_stage<T, N, 8, 64>(xr, xi, tw, lane, on);
   } else {
     static_assert(N == 1024, "N = 256, 512 or 1024");
-    fft_stage<T, N, 8, 1>(xr, xi, tw, lane);
-    fft_stage<T, N, 8, 8>(xr, xi, tw, lane);
-    fft_stage<T, N, 4, 64>(xr, xi, tw, lane);
-    fft_stage<T, N, 4, 256>(xr, xi, tw, lane);
+    fft_stage<T, N, 8, 1>(xr, xi, tw, lane, on);
+    fft_stage<T, N, 8, 8>(xr, xi, tw, lane, on);
+    fft_stage<T, N, 4, 64>(xr, xi, tw, lane, on);
+    fft_stage<T, N, 4, 256>(xr, xi, tw, lane, on);
   }
 }
 
 // Lines per tile of an FFT axis and the LDS the kernels need: tiles hold W
 // lines of spt species (x axis: spt = S, W = 2 for S <= 2 else 1; strided
-// axes: spt = 1, W = 4), one wavefront per pair of the tile's spt * W lines.
+// axes: spt = 1, W = 4), one wavefront per pair of the tile's spt * W lines;
+// the block has FFT_THREADS threads (at least one wavefront per pair), all of
+// which take part in the tile's loads, stores and pointwise stages.
+constexpr int FFT_THREADS = 256;
 __host__ __device__ constexpr int fft_pairs(int spt, int W) { return (spt * W + 1) / 2; }
 template <typename T>
 constexpr size_t fft_lds_bytes(int spt, int n, int W, int pitch) {
@@ -154,8 +164,8 @@ constexpr size_t fft_lds_bytes(int spt, int n, int W, int pitch) {
 }
 
 // The transform functor of the tile kernels (kernels.h): Hartley transform of
-// every line of the tile buf[s][j][w], in place. The block has one wavefront
-// per line pair; the pair buffers follow the tile in LDS.
+// every line of the tile buf[s][j][w], in place. Wavefront q < pairs runs the
+// pair of lines 2q, 2q + 1; the pair buffers follow the tile in LDS.
 template <typename T>
 struct FftXf {
   const Geom* g;
@@ -164,27 +174,32 @@ struct FftXf {
     const int n = g->n, W = g->W, pitch = g->pitch;
     const int L = S * W;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    T* xr = buf + (size_t)S * n * pitch + (size_t)wave * 2 * n;
-    T* xi = xr + n;
+    const bool on = wave < fft_pairs(S, W);
     const int l0 = 2 * wave, l1 = 2 * wave + 1;
     const bool has1 = l1 < L;
+    T* xr = buf + (size_t)S * n * pitch + (size_t)(on ? wave : 0) * 2 * n;
+    T* xi = xr + n;
     T* a = buf + (size_t)(l0 / W) * n * pitch + (l0 % W);
     T* b = buf + (size_t)(l1 / W) * n * pitch + (l1 % W);
-    for (int j = lane; j < n; j += 64) {
-      xr[j] = a[j * pitch];
-      xi[j] = has1 ? b[j * pitch] : T(0);
+    if (on) {
+      for (int j = lane; j < n; j += 64) {
+        xr[j] = a[j * pitch];
+        xi[j] = has1 ? b[j * pitch] : T(0);
+      }
     }
     __syncthreads();
     switch (n) {
-      case 256: fft_wave<T, 256>(xr, xi, tw, lane); break;
-      case 512: fft_wave<T, 512>(xr, xi, tw, lane); break;
-      default: fft_wave<T, 1024>(xr, xi, tw, lane); break;
+      case 256: fft_wave<T, 256>(xr, xi, tw, lane, on); break;
+      case 512: fft_wave<T, 512>(xr, xi, tw, lane, on); break;
+      default: fft_wave<T, 1024>(xr, xi, tw, lane, on); break;
     }
-    for (int k = lane; k < n; k += 64) {
-      const int kk = (n - k) & (n - 1);
-      const T zr = xr[k], zi = xi[k], wr = xr[kk], wi = xi[kk];
-      a[k * pitch] = T(0.5) * ((zr + wr) - (zi - wi));
-      if (has1) b[k * pitch] = T(0.5) * ((zr - wr) + (zi + wi));
+    if (on) {
+      for (int k = lane; k < n; k += 64) {
+        const int kk = (n - k) & (n - 1);
+        const T zr = xr[k], zi = xi[k], wr = xr[kk], wi = xi[kk];
+        a[k * pitch] = T(0.5) * ((zr + wr) - (zi - wi));
+        if (has1) b[k * pitch] = T(0.5) * ((zr - wr) + (zi + wi));
+      }
     }
     __syncthreads();
   }

@@ -934,7 +934,9 @@ __device__ __forceinline__ void block_add_partials(double* red, const double (&p
 }
 
 // ---------------------------------------------------------------- tile bodies
-// XF is the per-axis transform applied in place to every species' tile.
+// XF is the per-axis transform applied in place to every species' tile. FAST:
+// full tiles move in 16-byte vectors with every load of a thread issued
+// before its first use, and the combine runs on vectors of strided tiles.
 template <bool FAST, typename T>
 __device__ __forceinline__ void tile_in(const Geom& g, long long tile, const T* src, T* buf, int S) {
   if (FAST)
@@ -1009,34 +1011,34 @@ struct DenseXf {
 };
 
 // X kernel, forward: inverse-x, reaction, forward-x (in place on P).
-template <typename T, template <typename> class XFT = DenseXf>
+template <typename T, template <typename> class XFT = DenseXf, bool FAST = false>
 __global__ __launch_bounds__(NTHREADS) void k_xstage(StageArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   XFT<T> xf{&a.g, a.Mt};
-  body_x<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
+  body_x<FAST>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
 }
 
 // Z kernel, forward: forward transform along the last axis, stage combine,
 // inverse transform (in place on P).
-template <typename T, template <typename> class XFT = DenseXf>
+template <typename T, template <typename> class XFT = DenseXf, bool FAST = false>
 __global__ __launch_bounds__(NTHREADS) void k_zstage(StageArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   XFT<T> xf{&a.g, a.Mt};
-  body_z<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
+  body_z<FAST>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
 }
 
 // X kernel, adjoint: inverse-x of the spectral cotangent of f(stage value),
 // transposed reaction Jacobian at the stored stage value, forward-x.
-template <typename T, template <typename> class XFT = DenseXf>
+template <typename T, template <typename> class XFT = DenseXf, bool FAST = false>
 __global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   XFT<T> xf{&a.g, a.Mt};
   double pacc[RXN_NP_MAX];
   for (int k = 0; k < RXN_NP_MAX; ++k) pacc[k] = 0.0;
-  body_xadj<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf, pacc);
+  body_xadj<FAST>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf, pacc);
   if (a.rp_acc) {
     __syncthreads();
     block_add_partials(reinterpret_cast<double*>(smem_raw), pacc, a.rxn.np, a.rp_acc);
@@ -1044,12 +1046,12 @@ __global__ __launch_bounds__(NTHREADS) void k_xadj(StageArgs<T> a) {
 }
 
 // Z kernel, adjoint: forward-z, adjoint combine, inverse-z.
-template <typename T, template <typename> class XFT = DenseXf>
+template <typename T, template <typename> class XFT = DenseXf, bool FAST = false>
 __global__ __launch_bounds__(NTHREADS) void k_zadj(StageArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   XFT<T> xf{&a.g, a.Mt};
-  body_zadj<false>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
+  body_zadj<FAST>(a, reinterpret_cast<T*>(smem_raw), blockIdx.x, xf);
 }
 
 // One transform along one axis, src -> dst (may alias), with optional
@@ -1077,7 +1079,7 @@ __device__ __forceinline__ void to_member(SingleArgs<T>& a) {
   a.dst += f;
 }
 
-template <typename T, template <typename> class XFT = DenseXf>
+template <typename T, template <typename> class XFT = DenseXf, bool FAST = false>
 __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1088,7 +1090,7 @@ __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
   // tiles hold g.spt species (strided axes may hold one, with the species
   // index in the outer block)
   const int S = g.spt;
-  load_tile(g, tile, a.src, buf, S);
+  tile_in<FAST>(g, tile, a.src, buf, S);
   __syncthreads();
   const int ne = g.n * g.W;
   if (a.pre_divide_w) {
@@ -1114,7 +1116,7 @@ __global__ __launch_bounds__(NTHREADS) void k_single(SingleArgs<T> a) {
     }
     __syncthreads();
   }
-  store_tile(g, tile, buf, a.dst, S);
+  tile_out<FAST>(g, tile, buf, a.dst, S);
 }
 
 // --------------------------------------------------------------------------

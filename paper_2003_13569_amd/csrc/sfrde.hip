@@ -548,7 +548,7 @@ int setup_fft_axis(sfrde_plan_s* p, int axis) {
   g.wshift = 0;
   while ((1 << g.wshift) < g.W) ++g.wshift;
   g.fast = 0;
-  p->thr_f[axis] = 64u * (unsigned)fft_pairs(g.spt, g.W);
+  p->thr_f[axis] = FFT_THREADS;  // >= 64 per line pair (at most 2 here)
   p->lds_f[axis] = fft_lds_bytes<T>(g.spt, g.n, g.W, g.pitch);
   if (p->lds_f[axis] > 160 * 1024) return SFRDE_OK;  // dense kernels
   const double pi = 3.14159265358979323846;
@@ -560,11 +560,11 @@ int setup_fft_axis(sfrde_plan_s* p, int axis) {
   TRY(dev_alloc(p, &p->tw[axis], tw.size() * sizeof(T)));
   HIPCHECK(hipMemcpy(p->tw[axis], tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
   std::vector<const void*> fns = {
-      reinterpret_cast<const void*>(&k_xstage<T, FftXf>),
-      reinterpret_cast<const void*>(&k_zstage<T, FftXf>),
-      reinterpret_cast<const void*>(&k_xadj<T, FftXf>),
-      reinterpret_cast<const void*>(&k_zadj<T, FftXf>),
-      reinterpret_cast<const void*>(&k_single<T, FftXf>)};
+      reinterpret_cast<const void*>(&k_xstage<T, FftXf, true>),
+      reinterpret_cast<const void*>(&k_zstage<T, FftXf, true>),
+      reinterpret_cast<const void*>(&k_xadj<T, FftXf, true>),
+      reinterpret_cast<const void*>(&k_zadj<T, FftXf, true>),
+      reinterpret_cast<const void*>(&k_single<T, FftXf, true>)};
   for (const void* f : fns)
     HIPCHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)p->lds_f[axis]));
@@ -699,7 +699,7 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
                          p->mfax[axis]);
     }
   } else if (p->use_f[axis]) {
-    hipLaunchKernelGGL((k_single<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B),
+    hipLaunchKernelGGL((k_single<T, FftXf, true>), dim3((unsigned)a.g.ntiles, p->B),
                        dim3(p->thr_f[axis]), p->lds_f[axis], p->stream, a);
   } else
     hipLaunchKernelGGL(k_single<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
@@ -746,7 +746,7 @@ int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
       hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
   } else if (p->use_f[0]) {
-    hipLaunchKernelGGL((k_xstage<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[0]),
+    hipLaunchKernelGGL((k_xstage<T, FftXf, true>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[0]),
                        p->lds_f[0], p->stream, a);
   } else
     hipLaunchKernelGGL(k_xstage<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
@@ -806,7 +806,7 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_fhat, T* uhat = n
                          dim3(p->grid_m[ax], p->B), p->lds_m[ax], p->stream, a, p->mfax[ax]);
     }
   else if (p->use_f[ax]) {
-    hipLaunchKernelGGL((k_zstage<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[ax]),
+    hipLaunchKernelGGL((k_zstage<T, FftXf, true>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[ax]),
                        p->lds_f[ax], p->stream, a);
   } else
     hipLaunchKernelGGL(k_zstage<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
@@ -975,7 +975,7 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
   } else if (p->use_f[0]) {
-    hipLaunchKernelGGL((k_xadj<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[0]),
+    hipLaunchKernelGGL((k_xadj<T, FftXf, true>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[0]),
                        p->lds_f[0], p->stream, a);
   } else
     hipLaunchKernelGGL(k_xadj<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
@@ -1024,7 +1024,7 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
       hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, false>), grid, block, p->lds_m[ax], p->stream, a,
                          p->mfax[ax]);
   } else if (p->use_f[ax]) {
-    hipLaunchKernelGGL((k_zadj<T, FftXf>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[ax]),
+    hipLaunchKernelGGL((k_zadj<T, FftXf, true>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[ax]),
                        p->lds_f[ax], p->stream, a);
   } else
     hipLaunchKernelGGL(k_zadj<T>, dim3((unsigned)a.g.ntiles, p->B), dim3(NTHREADS),
