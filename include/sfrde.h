@@ -177,7 +177,8 @@ int sfrde_resume(sfrde_plan_t plan, const void* ckpt, int64_t slot, void* state,
  * Jacobian transposed). ckpt must come from sfrde_integrate(nsteps, t0,
  * ckpt_every) with this plan's shape, dtype and species count. Segments of
  * ckpt_every steps are recomputed from their checkpoint (memory: about
- * 9 * ckpt_every fields of workspace).
+ * 9 * ckpt_every fields of workspace when kappa or alpha gradients are asked,
+ * 4 * ckpt_every when not).
  *   grad_uT     device [S][...] dtype: dLoss/du(T)
  *   grad_u0     device [S][...] dtype: receives dLoss/du(0) (NULL: skip)
  *   grad_kappa  host double[S] (NULL: skip)   dLoss/dkappa_s

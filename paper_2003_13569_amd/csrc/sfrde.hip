@@ -163,7 +163,9 @@ struct sfrde_plan_s {
   void* gu = nullptr;
   double* G = nullptr;
   void* seg = nullptr;
-  long long seg_steps = 0;
+  long long seg_steps = 0;   // steps the allocated segment store holds
+  long long seg_cap = 0;     // its size in fields of [B][S][total]
+  int seg_stride = 9;        // fields per step of the current backward (9, or 4 for u0 only)
   double* rp_acc = nullptr;
   double* red = nullptr;  // reduction scratch
   long long red_len = 0;
@@ -723,10 +725,12 @@ StepStore<T> step_store(sfrde_plan_s* p, long long slot) {
   StepStore<T> s{nullptr, nullptr, nullptr};
   if (!p->seg) return s;
   const size_t f = field_elems(p);
-  T* base = (T*)p->seg + (size_t)slot * 9 * f;
+  T* base = (T*)p->seg + (size_t)slot * p->seg_stride * f;
   s.phys = base;
-  s.uhat = base + 4 * f;
-  s.fhat = base + 5 * f;
+  if (p->seg_stride == 9) {  // u_hat and the four f_hat: the kappa/alpha terms
+    s.uhat = base + 4 * f;
+    s.fhat = base + 5 * f;
+  }
   return s;
 }
 
@@ -1113,8 +1117,9 @@ int carve_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_theta
   take(&p->aacc, f);
   take(&p->ahat, f);
   take(&p->gu, f);
-  take(&p->seg, (size_t)seg_steps * 9 * f);
+  take(&p->seg, (size_t)seg_steps * p->seg_stride * f);
   p->seg_steps = seg_steps;
+  p->seg_cap = seg_steps * p->seg_stride;
   p->thp = nullptr;
   p->G = nullptr;
   p->dcoef = nullptr;
@@ -1148,11 +1153,16 @@ int ensure_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_thet
   TRY(dev_alloc(p, &p->aacc, f));
   TRY(dev_alloc(p, &p->ahat, f));
   TRY(dev_alloc(p, &p->gu, f));
-  if (p->seg && p->seg_steps < seg_steps) dev_free(p, &p->seg, (size_t)p->seg_steps * 9 * f);
-  if (!p->seg) {
-    TRY(dev_alloc(p, &p->seg, (size_t)seg_steps * 9 * f));
-    p->seg_steps = seg_steps;
+  const long long seg_need = seg_steps * p->seg_stride;
+  if (p->seg && p->seg_cap < seg_need) {
+    dev_free(p, &p->seg, (size_t)p->seg_cap * f);
+    p->seg_cap = 0;
   }
+  if (!p->seg) {
+    TRY(dev_alloc(p, &p->seg, (size_t)seg_need * f));
+    p->seg_cap = seg_need;
+  }
+  p->seg_steps = seg_steps;
   if (want_theta && p->thp_on) {
     TRY(dev_alloc(p, (void**)&p->thp, (size_t)4 * p->grid_m[p->ndim - 1] * sizeof(double)));
   } else if (want_theta) {
@@ -1181,6 +1191,9 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
   const bool want_theta = gk || ga;
   const bool want_p = gp != nullptr && p->rxn.np > 0;
   const long long seg_steps = std::min(K, nsteps);
+  // the recompute stores the stage values; u_hat and the four f_hat only for
+  // the kappa/alpha terms
+  p->seg_stride = want_theta ? 9 : 4;
   // kappa/alpha gradients formed inside the vector adjoint Z kernels (L
   // formed there too), else through the per-point accumulator G
   p->thp_on = want_theta && p->lfly && p->B == 1 && p->S <= 2 && use_fast<T>(p, p->ndim - 1, {});
@@ -1214,17 +1227,20 @@ int backward_t(sfrde_plan_s* p, const void* ckpt, long long nsteps, long long K,
       const long long k0 = sgi * K, k1 = std::min(nsteps, k0 + K);
       // the segment's u_hat of step k sits in store slot k - k0, that of its
       // first step in the checkpoint itself (read in place)
+      // (without the kappa/alpha terms u_hat is not stored: the recompute
+      // runs on the plan's own)
       T* ck = reinterpret_cast<T*>(ckpt_slot(p, (void*)ckpt, sgi));
+      const bool keep_uhat = p->seg_stride == 9;
       auto store_at = [&](long long k) {
         StepStore<T> st = step_store<T>(p, k - k0);
-        if (k == k0) st.uhat = ck;
+        if (k == k0 && keep_uhat) st.uhat = ck;
         return st;
       };
-      if ((rc = prologue_spectral<T>(p, ck, false))) break;
+      if ((rc = prologue_spectral<T>(p, ck, !keep_uhat))) break;
       for (long long k = k0; k < k1 && rc == SFRDE_OK; ++k) {
         StepStore<T> st = store_at(k);
         T* out = k + 1 < k1 ? store_at(k + 1).uhat : (T*)p->uhat;
-        rc = run_step<T>(p, t0 + double(k) * p->dt, &st, st.uhat, out);
+        rc = run_step<T>(p, t0 + double(k) * p->dt, &st, st.uhat, keep_uhat ? out : nullptr);
       }
       for (long long k = k1 - 1; k >= k0 && rc == SFRDE_OK; --k) {
         StepStore<T> st = store_at(k);
@@ -1636,7 +1652,7 @@ int sfrde_backward_noalloc(sfrde_plan_t p, const void* ckpt, int64_t nsteps,
   // the plan's own backward buffers are set aside for this call
   void* saved[] = {p->Pa, p->zh, p->aacc, p->ahat, p->gu, p->seg, p->G, p->dcoef, p->rp_acc,
                    p->thp, p->red};
-  const long long saved_seg = p->seg_steps, saved_red = p->red_len;
+  const long long saved_seg = p->seg_steps, saved_red = p->red_len, saved_cap = p->seg_cap;
   p->noalloc = true;
   int rc;
   if (p->dtype == SFRDE_F32)
@@ -1658,6 +1674,7 @@ int sfrde_backward_noalloc(sfrde_plan_t p, const void* ckpt, int64_t nsteps,
   p->thp = (double*)saved[9];
   p->red = (double*)saved[10];
   p->seg_steps = saved_seg;
+  p->seg_cap = saved_cap;
   p->red_len = saved_red;
   return rc;
 }

@@ -322,3 +322,36 @@ def test_config5_fp64_adjoint_matches_central_differences():
               f"h/2 {abs(g - cds[1]) / abs(ref):.2e}")
         print(f"config5 FD {which}[{i}]: adjoint {g:.12e} central {ref:.12e} rel {err:.2e}")
         assert err <= C5_FD_TOL, (which, i, g, ref)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("wl", [CASES[2], VEC_CASES[0]], ids=["gm2d-neu", "sch3d-neu-vec"])
+def test_u0_only_backward_matches_full_backward(wl, dtype):
+    # without kappa/alpha gradients the recompute stores 4 fields per step
+    # (no u_hat, no f_hat) and runs on the plan's own u_hat
+    u0 = W.initial_fields(wl)
+    wbar = np.random.default_rng(31).standard_normal(u0.shape)
+    p = plan_for(wl, dtype)
+    u = torch.tensor(u0, dtype=TD[dtype], device="cuda")
+    ck = p.integrate(u, M, 0.0, ckpt_every=K)
+    g = torch.tensor(wbar, dtype=TD[dtype], device="cuda")
+    a, b = torch.empty_like(g), torch.empty_like(g)
+    full_bytes = None
+    p.backward(ck, M, K, g, 0.0, a)
+    full_bytes = p.workspace_bytes()
+    gk, ga, gp = p.backward(ck, M, K, g, 0.0, b, kappa=False, alpha=False, params=False)
+    assert gk is None and ga is None and gp is None
+    torch.cuda.synchronize()
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert _rel(b.double().cpu().numpy(), a.double().cpu().numpy()) <= tol
+    # a fresh plan asked for u0 only holds the smaller store
+    q = plan_for(wl, dtype)
+    v = torch.tensor(u0, dtype=TD[dtype], device="cuda")
+    ck2 = q.integrate(v, M, 0.0, ckpt_every=K)
+    c = torch.empty_like(g)
+    q.backward(ck2, M, K, g, 0.0, c, kappa=False, alpha=False, params=False)
+    torch.cuda.synchronize()
+    assert torch.equal(c, b)
+    assert q.workspace_bytes() < full_bytes
+    p.close()
+    q.close()
