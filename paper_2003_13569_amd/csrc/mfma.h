@@ -790,6 +790,17 @@ __device__ __forceinline__ bool x_reaction_fast(const StageArgs<float>& a, float
   return pw_reaction(a, buf, tile, false);
 }
 
+// The reaction of the register-fed x kernels: kind RK when the launch fixes
+// it (RK >= 0), else chosen at run time.
+template <int RK>
+__device__ __forceinline__ bool x_reaction_sel(const StageArgs<float>& a, float* buf,
+                                               long long tile) {
+  if constexpr (RK >= 0)
+    return x_reaction_vec<2, RK>(a, buf);
+  else
+    return x_reaction_fast(a, buf, tile);
+}
+
 __device__ __forceinline__ void xadj_reaction_fast(const StageArgs<float>& a, float* buf,
                                                    long long tile, double* pacc) {
   switch (a.S) {
@@ -1348,7 +1359,11 @@ struct XFoldLoads {
 // after its stores: the wait then covers those loads only (the stores just
 // issued stay in flight), on the one path through the loop body. Past the
 // last tile, the last one is loaded again and dropped.
-template <typename T, class XF, bool FAST>
+// RK >= 0 (FAST FP32, two species, non-periodic x axis: the host checks):
+// only the register-fed path with reaction kind RK is compiled. A kernel
+// holding every path and kind is several times the size of the instruction
+// cache, and each launch then waits on instruction fetches.
+template <typename T, class XF, bool FAST, int RK = -1>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(StageArgs<T> a, MfmaAxisDev ax) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1358,7 +1373,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
   const long long last = a.g.ntiles - 1;
   bool bad = false;
   if constexpr (FAST && std::is_same<T, float>::value) {
-    if (ax.direct && S == 2) {
+    if (RK >= 0 || (ax.direct && S == 2)) {
       // inverse-x folded straight from registers: no LDS staging of the input
       XFoldLoads rl;
       rl.issue(a.g, blockIdx.x, a.P);
@@ -1376,7 +1391,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
                                 a.st_phys + (long long)a.mode * S * a.g.total);
           __syncthreads();
         }
-        bad |= x_reaction_fast(a, buf, tile);
+        bad |= x_reaction_sel<RK>(a, buf, tile);
         __syncthreads();
         xf(buf, S);
         tile_store<T, XF::W, FAST, true>(a.g, tile, buf, a.P);
@@ -1386,6 +1401,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
       return;
     }
   }
+  if constexpr (RK >= 0) return;
   TilePipe<T, XF::W, FAST, true> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
   pipe.commit(a.g, blockIdx.x, a.P, buf);
@@ -1625,7 +1641,10 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
 
 // One transform along one axis, src -> dst (may alias), optional Neumann
 // point weights before (divide) or after (multiply).
-template <typename T, class XF, bool FAST>
+// PATH (FAST FP32 launches without point weights, chosen by the host): 1 =
+// results straight to global memory (DCT-I / DST-I on one-species tiles),
+// 2 = through the tile; only that path is compiled. 0: every path.
+template <typename T, class XF, bool FAST, int PATH = 0>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(SingleArgs<T> a, MfmaAxisDev ax) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1635,7 +1654,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
   const int ne = g.n * g.W;
   const long long last = g.ntiles - 1;
   if constexpr (FAST && std::is_same<T, float>::value) {
-    if (!a.pre_divide_w && !a.post_multiply_w) {
+    if (PATH != 0 || (!a.pre_divide_w && !a.post_multiply_w)) {
       // two tiles in flight: pipes A and B alternate
       TilePipe<T, XF::W, FAST, XF::XAX> pa, pb;
       const long long G = gridDim.x;
@@ -1645,7 +1664,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
       pa.commit(g, blockIdx.x, a.src, buf);
       __syncthreads();
       // results of DCT-I / DST-I transforms go straight to global memory
-      const bool direct = ax.direct != 0 && g.spt == 1;
+      const bool direct = PATH == 1 || (PATH == 0 && ax.direct != 0 && g.spt == 1);
       for (long long tile = blockIdx.x; tile < g.ntiles; tile += 2 * G) {
         pa.issue(g, nxt(tile + 2 * G), a.src);
         if (direct) {
@@ -1672,6 +1691,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
       return;
     }
   }
+  if constexpr (PATH != 0) return;
   TilePipe<T, XF::W, FAST, XF::XAX> pipe;
   pipe.issue(g, blockIdx.x, a.src);
   pipe.commit(g, blockIdx.x, a.src, buf);

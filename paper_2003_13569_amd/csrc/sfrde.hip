@@ -602,7 +602,16 @@ int set_lds_attrs(size_t bytes) {
                           reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 3>),
                           reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, MODE_INIT>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true>),
-                          reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true>)};
+                          reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true>),
+                          reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true, 1>),
+                          reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true, 1>),
+                          reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true, 2>),
+                          reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true, 2>),
+                          reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>, true, RXN_LINEAR>),
+                          reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>, true, RXN_FHN>),
+                          reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>, true, RXN_GRAY_SCOTT>),
+                          reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>, true, RXN_SCHNAKENBERG>),
+                          reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>, true, RXN_GM>)};
     for (const void* f : fast) fns.push_back(f);
   }
   for (const void* f : fns)
@@ -679,12 +688,23 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
     const dim3 grid(p->grid_m[axis], p->B);
     const size_t lds = p->lds_m[axis];
     const bool fast = use_fast<T>(p, axis, {src, dst});
+    // fast launches without point weights: the kernel holding only the
+    // tile path that runs
+    const bool plain = fast && !a.pre_divide_w && !a.post_multiply_w;
+    const bool to_glob = p->mfax[axis].direct != 0 && a.g.spt == 1;
     if (axis == 0) {
       const dim3 block(XfX<T>::THREADS);
       if constexpr (std::is_same<T, float>::value)
         if (fast) {
-          hipLaunchKernelGGL((k_single_m<T, XfX<T>, true>), grid, block, lds, p->stream, a,
-                             p->mfax[axis]);
+          if (plain && to_glob)
+            hipLaunchKernelGGL((k_single_m<T, XfX<T>, true, 1>), grid, block, lds, p->stream, a,
+                               p->mfax[axis]);
+          else if (plain)
+            hipLaunchKernelGGL((k_single_m<T, XfX<T>, true, 2>), grid, block, lds, p->stream, a,
+                               p->mfax[axis]);
+          else
+            hipLaunchKernelGGL((k_single_m<T, XfX<T>, true>), grid, block, lds, p->stream, a,
+                               p->mfax[axis]);
           goto launched;
         }
       hipLaunchKernelGGL((k_single_m<T, XfX<T>, false>), grid, block, lds, p->stream, a,
@@ -693,8 +713,15 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
       const dim3 block(XfZ<T>::THREADS);
       if constexpr (std::is_same<T, float>::value)
         if (fast) {
-          hipLaunchKernelGGL((k_single_m<T, XfZ<T>, true>), grid, block, lds, p->stream, a,
-                             p->mfax[axis]);
+          if (plain && to_glob)
+            hipLaunchKernelGGL((k_single_m<T, XfZ<T>, true, 1>), grid, block, lds, p->stream, a,
+                               p->mfax[axis]);
+          else if (plain)
+            hipLaunchKernelGGL((k_single_m<T, XfZ<T>, true, 2>), grid, block, lds, p->stream, a,
+                               p->mfax[axis]);
+          else
+            hipLaunchKernelGGL((k_single_m<T, XfZ<T>, true>), grid, block, lds, p->stream, a,
+                               p->mfax[axis]);
           goto launched;
         }
       hipLaunchKernelGGL((k_single_m<T, XfZ<T>, false>), grid, block, lds, p->stream, a,
@@ -743,12 +770,33 @@ int launch_x(sfrde_plan_s* p, int stage, double t, T* st_phys) {
   const long long pk = prof_start(p, KC_X);
   if (p->use_m[0]) {
     const dim3 grid(p->grid_m[0], p->B), block(XfX<T>::THREADS);
-    if (use_fast<T>(p, 0, {p->P, st_phys}))
+    const bool fast = use_fast<T>(p, 0, {p->P, st_phys});
+    // FP32, two species, non-periodic x: the register-fed kernel of the
+    // plan's reaction kind
+    const int rk = std::is_same<T, float>::value && fast && p->S == 2 &&
+                           p->bc != SFRDE_BC_PERIODIC && p->rxn.kind <= RXN_GM
+                       ? p->rxn.kind
+                       : -1;
+    if constexpr (std::is_same<T, float>::value) {
+      if (rk >= 0) {
+        const size_t lds = p->lds_m[0];
+        switch (rk) {
+          case RXN_LINEAR: hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, true, RXN_LINEAR>), grid, block, lds, p->stream, a, p->mfax[0]); break;
+          case RXN_FHN: hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, true, RXN_FHN>), grid, block, lds, p->stream, a, p->mfax[0]); break;
+          case RXN_GRAY_SCOTT: hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, true, RXN_GRAY_SCOTT>), grid, block, lds, p->stream, a, p->mfax[0]); break;
+          case RXN_SCHNAKENBERG: hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, true, RXN_SCHNAKENBERG>), grid, block, lds, p->stream, a, p->mfax[0]); break;
+          default: hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, true, RXN_GM>), grid, block, lds, p->stream, a, p->mfax[0]); break;
+        }
+        goto x_launched;
+      }
+    }
+    if (fast)
       hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, std::is_same<T, float>::value>), grid, block,
                          p->lds_m[0], p->stream, a, p->mfax[0]);
     else
       hipLaunchKernelGGL((k_xstage_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
+  x_launched:;
   } else if (p->use_f[0]) {
     hipLaunchKernelGGL((k_xstage<T, FftXf, true>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[0]),
                        p->lds_f[0], p->stream, a);
