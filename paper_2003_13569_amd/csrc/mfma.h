@@ -9,10 +9,11 @@
 // DCT/DST, y_k = (Es)_k + (Od)_k and y_{N-k} = (Es)_k - (Od)_k for Hartley.
 // That halves the multiply-adds of the dense product.
 //
-// The half-size matrices live in registers of a persistent block of 16
-// waves: wave w owns 16 rows of E (w < RBe) or of O, for all K. Per tile of
-// W lines the block folds the data in LDS, each wave runs its row block over
-// all lines, results go back to LDS and are unfolded into the tile.
+// The half-size matrices live in registers of a persistent block of 8
+// waves, one block per CU: wave w owns the 16-row blocks 2w and 2w + 1 of E
+// (block index < RBe) or of O, for all K. Per tile of W lines the block folds
+// the data in LDS, each wave runs its row blocks over all lines, results go
+// back to LDS and are unfolded into the tile.
 //
 // FP32 fields: products on v_mfma_f32_16x16x32_f16 with both operands split
 // into two binary16 terms after a per-column power-of-two scaling, three
@@ -28,8 +29,7 @@
 
 namespace sfrde {
 
-constexpr int MF_THREADS = 1024;  // 16 waves
-constexpr int MF_WAVES = 16;
+constexpr int MF_WAVES = 16;      // 16-row blocks of E and O at most (two per wave)
 constexpr int MF_KSMAX_F32 = 4;   // K <= 128 in steps of 32
 constexpr int MF_KSMAX_F64 = 32;  // K <= 128 in steps of 4
 
@@ -65,34 +65,6 @@ __device__ __forceinline__ void fold_pair(const MfmaAxisDev& ax, int i, int& a, 
     b = 2 * i + 1 < ax.n ? ax.n - 1 - i : -1;
   else
     b = (i == 0 || 2 * i == ax.n) ? -1 : ax.n - i;
-}
-
-// Fold every line of one species' tile into fb: s rows then d rows, each
-// [W][fb_pitch], eight consecutive i per work item.
-template <typename T, int W>
-__device__ __forceinline__ void mf_fold(const T* x, int pitch, const MfmaAxisDev& ax, T* fb) {
-  const int items = W * (ax.hK / 8);
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int col = it % W;
-    const int i0 = (it / W) * 8;
-    T sv[8], dv[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      int a, b;
-      fold_pair(ax, i0 + e, a, b);
-      const T xa = a >= 0 ? x[a * pitch + col] : T(0);
-      const T xb = b >= 0 ? x[b * pitch + col] : T(0);
-      sv[e] = xa + xb;
-      dv[e] = b >= 0 ? xa - xb : T(0);
-    }
-    T* ps = fb + col * ax.fb_pitch + i0;
-    T* pd = fb + (W + col) * ax.fb_pitch + i0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      ps[e] = sv[e];
-      pd[e] = dv[e];
-    }
-  }
 }
 
 // Hartley unfold of the result rows R[row][col] into the tile x[k][col]:
@@ -442,25 +414,67 @@ struct MfmaXfF32 {
 };
 
 // ------------------------------------------------------------------ FP64
+// Eight waves; wave w owns row blocks 2w and 2w + 1 (of E, then of O) for all
+// K, 2 x 32 fragments = 128 registers per lane, with one 512-thread block per
+// CU (256 registers per lane). Each row block runs two accumulation chains
+// (even and odd ks), so a wave keeps four MFMA chains in flight.
 struct MfmaXfF64 {
   static constexpr int W = 16;
-  static constexpr int THREADS = MF_THREADS;
-  static constexpr int MIN_WAVES_PER_EU = 4;
-  static constexpr bool XAX = false;  // generic tile paths on every axis
+  static constexpr int THREADS = 512;
+  static constexpr int MIN_WAVES_PER_EU = 2;  // one block per CU, 256 registers per lane
+  static constexpr bool XAX = false;          // generic tile paths on every axis
+  static constexpr int FOLD_E = 4;            // fold entries per work item
   const Geom* g;
   const MfmaAxisDev* ax;
   double* fb;
-  double A[MF_KSMAX_F64];
-  int wave, lane;
+  double A[2][MF_KSMAX_F64];
+  int wave, lane, nrb;
+  bool isO[2];
+  int bofs[2];  // B-fragment offsets in fb per row block
 
   __device__ __forceinline__ MfmaXfF64(const Geom* g_, const MfmaAxisDev* ax_, double* fb_)
       : g(g_), ax(ax_), fb(fb_) {
     wave = threadIdx.x / 64;
     lane = threadIdx.x % 64;
+    const int rb0 = 2 * wave;
+    nrb = ax->RB - rb0;
+    nrb = nrb < 0 ? 0 : (nrb > 2 ? 2 : nrb);
     const double* src = reinterpret_cast<const double*>(ax->Afrag);
 #pragma unroll
-    for (int ks = 0; ks < MF_KSMAX_F64; ++ks)
-      A[ks] = wave < ax->RB ? src[(wave * MF_KSMAX_F64 + ks) * 64 + lane] : 0.0;
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int ks = 0; ks < MF_KSMAX_F64; ++ks)
+        A[h][ks] = h < nrb ? src[((rb0 + h) * MF_KSMAX_F64 + ks) * 64 + lane] : 0.0;
+      isO[h] = rb0 + h >= ax->RBe;
+      bofs[h] = ((isO[h] ? W : 0) + lane % 16) * ax->fb_pitch + lane / 16;
+    }
+  }
+
+  // Fold of one species' tile into fb (s rows then d rows, [W][fb_pitch]),
+  // FOLD_E consecutive entries per work item, every thread taking part.
+  __device__ __forceinline__ void fold(const double* x, int pitch) {
+    const int items = W * (ax->hK / FOLD_E);
+    for (int it = threadIdx.x; it < items; it += THREADS) {
+      const int col = it % W;
+      const int i0 = (it / W) * FOLD_E;
+      double sv[FOLD_E], dv[FOLD_E];
+#pragma unroll
+      for (int e = 0; e < FOLD_E; ++e) {
+        int a, b;
+        fold_pair(*ax, i0 + e, a, b);
+        const double xa = a >= 0 ? x[a * pitch + col] : 0.0;
+        const double xb = b >= 0 ? x[b * pitch + col] : 0.0;
+        sv[e] = xa + xb;
+        dv[e] = b >= 0 ? xa - xb : 0.0;
+      }
+      double* ps = fb + col * ax->fb_pitch + i0;
+      double* pd = fb + (W + col) * ax->fb_pitch + i0;
+#pragma unroll
+      for (int e = 0; e < FOLD_E; e += 2) {
+        *reinterpret_cast<double2*>(ps + e) = make_double2(sv[e], sv[e + 1]);
+        *reinterpret_cast<double2*>(pd + e) = make_double2(dv[e], dv[e + 1]);
+      }
+    }
   }
 
   __device__ __forceinline__ void operator()(double* buf, int S) {
@@ -468,46 +482,60 @@ struct MfmaXfF64 {
     const int KS = ax->hK / 4;
     for (int s = 0; s < S; ++s) {
       double* x = buf + s * n * pitch;
-      mf_fold<double, W>(x, pitch, *ax, fb);
+      fold(x, pitch);
       __syncthreads();
-      f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
-      if (wave < ax->RB) {
-        const int half = wave < ax->RBe ? 0 : 1;
-        const double* bp = fb + (half * W + lane % 16) * ax->fb_pitch + lane / 16;
-        // four independent accumulators over ks mod 4 (the folded length is a
-        // multiple of 32, so KS is a multiple of 8): four MFMA chains in flight
-        // instead of one dependent chain of KS products
-        f64x4 acc1 = f64x4{0.0, 0.0, 0.0, 0.0}, acc2 = acc1, acc3 = acc1;
+      f64x4 acc[2];
 #pragma unroll
-        for (int ks = 0; ks < MF_KSMAX_F64; ks += 4) {
+      for (int h = 0; h < 2; ++h) acc[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+      if (nrb > 0) {
+        // two chains per row block over even and odd ks (KS is a multiple of
+        // 8: the folded length is a multiple of 32)
+        f64x4 acc1[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc1[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+        const double* bp0 = fb + bofs[0];
+        const double* bp1 = fb + bofs[1];
+#pragma unroll
+        for (int ks = 0; ks < MF_KSMAX_F64; ks += 2) {
           if (ks < KS) {
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks], bp[4 * ks], acc, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks + 1], bp[4 * ks + 4], acc1, 0, 0, 0);
-            acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks + 2], bp[4 * ks + 8], acc2, 0, 0, 0);
-            acc3 = __builtin_amdgcn_mfma_f64_16x16x4f64(A[ks + 3], bp[4 * ks + 12], acc3, 0, 0, 0);
+            const double b00 = bp0[4 * ks], b01 = bp0[4 * ks + 4];
+            const double b10 = bp1[4 * ks], b11 = bp1[4 * ks + 4];
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[0][ks], b00, acc[0], 0, 0, 0);
+            acc1[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[0][ks + 1], b01, acc1[0], 0, 0, 0);
+            if (nrb == 2) {
+              acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[1][ks], b10, acc[1], 0, 0, 0);
+              acc1[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(A[1][ks + 1], b11, acc1[1], 0, 0, 0);
+            }
           }
         }
-        acc = (acc + acc1) + (acc2 + acc3);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) acc[h] = acc[h] + acc1[h];
       }
       // f64 16x16x4 result layout: lane l, register r holds row 4r + l/16, column l%16
       if (ax->direct) {
         // DCT-I / DST-I: E row m is output 2m, O row m is output 2m + 1.
-        if (wave < ax->RB) {
-          const bool isO = wave >= ax->RBe;
-          const int mb = 16 * (isO ? wave - ax->RBe : wave) + lane / 16;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int k = 2 * (mb + 4 * r) + (isO ? 1 : 0);
-            if (k < n) x[k * pitch + lane % 16] = acc[r];
+        for (int h = 0; h < 2; ++h) {
+          if (h < nrb) {
+            const int rbl = 2 * wave + h - (isO[h] ? ax->RBe : 0);
+            const int mb = 16 * rbl + lane / 16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int k = 2 * (mb + 4 * r) + (isO[h] ? 1 : 0);
+              if (k < n) x[k * pitch + lane % 16] = acc[h][r];
+            }
           }
         }
         __syncthreads();
       } else {
         __syncthreads();
-        if (wave < ax->RB) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            fb[(16 * wave + 4 * r + lane / 16) * ax->r_pitch + lane % 16] = acc[r];
+        for (int h = 0; h < 2; ++h) {
+          if (h < nrb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              fb[(16 * (2 * wave + h) + 4 * r + lane / 16) * ax->r_pitch + lane % 16] = acc[h][r];
+          }
         }
         __syncthreads();
         mf_unfold<double, W>(fb, *ax, n, x, pitch);
@@ -810,6 +838,89 @@ __device__ __forceinline__ void xadj_reaction_fast(const StageArgs<float>& a, fl
   }
 }
 
+// FP64 tiles (W = 16 lines, 512 threads) moved through registers, CAP
+// vectors of two doubles per thread, when the launch allows it (g.fast, set
+// by the host for full tiles of at most two species, n a multiple of 64 up
+// to 256, 16-byte aligned fields) and the tile needs at most CAP vectors:
+//   strided axes: thread t moves columns 2(t%8), +1 of rows t/8 + 64k;
+//   x axis: consecutive threads move consecutive point pairs of a line.
+template <int CAP>
+struct TileIOF64 {
+  double2 v[CAP];
+  // vectors per thread: n/64 per species in both layouts
+  __device__ __forceinline__ static int nvec(const Geom& g) { return g.spt * (g.n >> 6); }
+  __device__ __forceinline__ static bool usable(const Geom& g) {
+    return g.fast && nvec(g) <= CAP;
+  }
+  // Vector m = s (n/64) + k of this thread (species s, block k) sits at
+  //   global  tile base + s total + gb + k gk,   LDS  s n pitch + lb + k lk:
+  // x tiles are contiguous per species (pair q = t + 512k at offset 2q, tile
+  // row 2(q mod n/2), column q / (n/2)); strided rows are t/8 + 64k.
+  struct Map {
+    long long gb, gk;
+    int lb, lk, ps, per;
+  };
+  __device__ __forceinline__ static Map map(const Geom& g) {
+    Map mp;
+    const int t = (int)threadIdx.x;
+    mp.per = g.n >> 6;
+    if (g.inner == 1) {
+      const int half = g.n >> 1;
+      mp.gb = 2 * t;
+      mp.gk = 1024;
+      mp.lb = 2 * (t & (half - 1)) * g.pitch + t / half;
+      mp.lk = 1024 / g.n;
+      mp.ps = g.pitch;  // the pair's two points are consecutive rows
+    } else {
+      mp.gb = (long long)(t >> 3) * g.inner + 2 * (t & 7);
+      mp.gk = 64 * g.inner;
+      mp.lb = (t >> 3) * g.pitch + 2 * (t & 7);
+      mp.lk = 64 * g.pitch;
+      mp.ps = 1;  // consecutive columns
+    }
+    return mp;
+  }
+  __device__ __forceinline__ void issue(const Geom& g, const TileRef& tr, const double* src) {
+    const Map mp = map(g);
+    const int nv = nvec(g);
+    const double* sp = src + tr.base + mp.gb;
+#pragma unroll
+    for (int m = 0; m < CAP; ++m) {
+      if (m < nv) {
+        const int s = m / mp.per, k = m - s * mp.per;
+        v[m] = *reinterpret_cast<const double2*>(sp + s * g.total + k * mp.gk);
+      }
+    }
+  }
+  __device__ __forceinline__ void commit(const Geom& g, double* buf) const {
+    const Map mp = map(g);
+    const int nv = nvec(g);
+#pragma unroll
+    for (int m = 0; m < CAP; ++m) {
+      if (m < nv) {
+        const int s = m / mp.per, k = m - s * mp.per;
+        double* b = buf + s * g.n * g.pitch + mp.lb + k * mp.lk;
+        b[0] = v[m].x;
+        b[mp.ps] = v[m].y;
+      }
+    }
+  }
+  __device__ __forceinline__ static void store(const Geom& g, const TileRef& tr, const double* buf,
+                                               double* dst) {
+    const Map mp = map(g);
+    const int nv = nvec(g);
+    double* dp = dst + tr.base + mp.gb;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      if (m < nv) {
+        const int s = m / mp.per, k = m - s * mp.per;
+        const double* b = buf + s * g.n * g.pitch + mp.lb + k * mp.lk;
+        *reinterpret_cast<double2*>(dp + s * g.total + k * mp.gk) = make_double2(b[0], b[mp.ps]);
+      }
+    }
+  }
+};
+
 // Register prefetch of a tile. FAST kernels (chosen by the host when every
 // tile is full, the shapes fit the layouts above and the pointers are
 // 16-byte aligned) move tiles with TileIO only; the others with the generic
@@ -833,10 +944,35 @@ struct TilePipe {
   }
 };
 
+// FP64 matrix-core tiles: the next tile in registers where TileIOF64 applies
+// (x-axis kernels hold up to 8 vectors per thread, the others 4), else the
+// generic in-place loads.
+template <bool XAX>
+struct TilePipe<double, 16, false, XAX> {
+  using IO = TileIOF64<XAX ? 8 : 4>;
+  IO io;
+  __device__ __forceinline__ void issue(const Geom& g, long long tile, const double* src) {
+    if (IO::usable(g)) io.issue(g, tile_ref(g, tile < g.ntiles ? tile : g.ntiles - 1), src);
+  }
+  __device__ __forceinline__ void commit(const Geom& g, long long tile, const double* src,
+                                         double* buf) {
+    if (IO::usable(g))
+      io.commit(g, buf);
+    else
+      load_tile_fast(g, tile, src, buf, g.spt);
+  }
+};
+
 template <typename T, int W, bool FAST, bool XAX>
 __device__ __forceinline__ void tile_store(const Geom& g, long long tile, const T* buf, T* dst) {
   using IO = typename std::conditional<XAX && std::is_same<T, float>::value, XTileIO<W>,
                                        TileIO<T, W>>::type;
+  if constexpr (std::is_same<T, double>::value && !FAST) {
+    if (g.fast && TileIOF64<8>::nvec(g) <= 8) {
+      TileIOF64<8>::store(g, tile_ref(g, tile), buf, dst);
+      return;
+    }
+  }
   if (FAST)
     IO::store(g, tile_ref(g, tile), buf, dst);
   else

@@ -462,8 +462,9 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
              (long long)p->S * g.n >= 64 && g.outer % W == 0;
   else if (f32)
     g.fast = g.inner % W == 0 && g.n % 64 == 0 && g.n <= 256;
-  else
-    g.fast = 0;
+  else  // FP64: full tiles of at most two species move through registers (TileIOF64)
+    g.fast = g.n % 64 == 0 && g.n <= 256 && g.spt <= 2 &&
+             (g.inner == 1 ? g.outer % W == 0 : g.inner % W == 0);
   MfmaAxisDev& ax = p->mfax[axis];
   ax.hK = t.hK;
   ax.RBe = t.RBe;
@@ -668,10 +669,20 @@ bool use_fast(const sfrde_plan_s* p, int axis, std::initializer_list<const void*
   return true;
 }
 
+// FP64 matrix-core launches move tiles through registers only with 16-byte
+// aligned fields (the plan's own buffers always are).
+template <typename T>
+void align_check(Geom& g, std::initializer_list<const void*> ptrs) {
+  if (std::is_same<T, float>::value) return;
+  for (const void* q : ptrs)
+    if (reinterpret_cast<uintptr_t>(q) & 15u) g.fast = 0;
+}
+
 template <typename T>
 int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre_div, int post_mul) {
   SingleArgs<T> a{};
   a.g = p->use_m[axis] ? p->geom_m[axis] : p->use_f[axis] ? p->geom_f[axis] : p->geom[axis];
+  align_check<T>(a.g, {src, dst});
   a.Mt = (const T*)(p->use_f[axis] ? p->tw[axis] : p->Mt[axis]);
   a.src = (const T*)src;
   a.dst = (T*)dst;
@@ -844,6 +855,7 @@ int launch_z(sfrde_plan_s* p, int mode, const void* src, T* st_fhat, T* uhat = n
   StageArgs<T> a = stage_args<T>(p, ax, p->P);
   a.mode = mode;
   a.src = (const T*)src;
+  align_check<T>(a.g, {src});
   a.st_fhat = st_fhat;
   if (uhat) a.uhat = uhat;
   const long long pk = prof_start(p, KC_Z);
