@@ -45,6 +45,7 @@ struct MfmaAxisDev {
   int r_pitch;            // row pitch of the result buffer (elements)
   int fb_off;             // byte offset of the fold/result area in LDS
   int direct;             // unfold is the even/odd row interleave (DCT-I, DST-I)
+  int nfb;                // FP32 fold buffers in LDS (2 where they fit on the x axis, else 1)
 };
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -140,9 +141,14 @@ struct MfmaXfF32 {
   static constexpr int TS = 2 * W * F32_FBP;  // binary16 elements between the two terms
   static constexpr int FOLD_THREADS = 16 * W; // one 16-lane row per column
   static constexpr int CB = W / 16;           // 16-column blocks
+  // Fold buffers: x tiles (every species) alternate two where LDS allows
+  // (ax->nfb), so that one species' fold can run while other waves still
+  // multiply the previous one.
+  static constexpr int FBH = f32_fold_bytes(W) / 2;  // binary16 elements per buffer
   const MfmaAxisDev* ax;
-  unsigned short* fb;
-  float* scl;  // inverse column scales
+  unsigned short* fb0;
+  unsigned short* fb;  // the buffer in use
+  float* scl;          // its inverse column scales
   f16x8 A[2][MF_KSMAX_F32][2];
   int n, KS;
   int nrb;      // row blocks of this wave (0..2)
@@ -156,8 +162,8 @@ struct MfmaXfF32 {
   int rmask[2], orow[2];
 
   __device__ __forceinline__ MfmaXfF32(const Geom*, const MfmaAxisDev* ax_, float* fb_)
-      : ax(ax_), fb(reinterpret_cast<unsigned short*>(fb_)) {
-    scl = reinterpret_cast<float*>(fb + 2 * TS);
+      : ax(ax_), fb0(reinterpret_cast<unsigned short*>(fb_)) {
+    use(0);
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     n = ax->n;
     KS = ax->hK >> 5;
@@ -202,6 +208,13 @@ struct MfmaXfF32 {
     fa = i0 * P + col;
     fbb = (bstart - i0) * P + col;
   }
+
+  // Select fold buffer b mod nfb for the next fold and products.
+  __device__ __forceinline__ void use(int b) {
+    fb = fb0 + (XAX && ax->nfb > 1 ? (b & 1) * FBH : 0);
+    scl = reinterpret_cast<float*>(fb + 2 * TS);
+  }
+  __device__ __forceinline__ bool two_buffers() const { return XAX && ax->nfb > 1; }
 
   __device__ __forceinline__ void fold(const float* x) {
     if ((int)threadIdx.x >= FOLD_THREADS) return;
@@ -365,14 +378,20 @@ struct MfmaXfF32 {
   __device__ __forceinline__ void operator()(float* buf, int S) {
     for (int s = 0; s < S; ++s) {
       float* x = buf + s * n * P;
+      use(s);
       fold(x);
       __syncthreads();
-      mfma_write(x);
+      // With two buffers the next species' fold (other rows of the tile, the
+      // other buffer) needs no barrier after these products; the barrier
+      // after the last species covers every result.
+      mfma_write(x, !two_buffers() || s == S - 1);
     }
+    use(0);
   }
 
-  // Products of the folded data in fb and their unfold into the tile x.
-  __device__ __forceinline__ void mfma_write(float* x) {
+  // Products of the folded data in fb and their unfold into the tile x;
+  // sync: a barrier after the results (the unfold path always has one).
+  __device__ __forceinline__ void mfma_write(float* x, bool sync = true) {
     const int lane = threadIdx.x % 64;
     {
       f32x4 acc[2][CB];
@@ -389,7 +408,7 @@ struct MfmaXfF32 {
             }
           }
         }
-        __syncthreads();
+        if (sync) __syncthreads();
       } else {
         float* R = reinterpret_cast<float*>(fb);
         const int rb0 = 2 * (threadIdx.x / 64);
@@ -1517,11 +1536,13 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
         const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
         xf.fold_regs(rl.v[0]);
         __syncthreads();
-        xf.mfma_write(buf);
+        xf.mfma_write(buf, !xf.two_buffers());
+        xf.use(1);
         xf.fold_regs(rl.v[1]);
         rl.issue(a.g, next, a.P);
         __syncthreads();
         xf.mfma_write(buf + a.g.n * XF::P);
+        xf.use(0);
         if (a.st_phys) {
           XTileIO<XF::W>::store(a.g, tile_ref(a.g, tile), buf,
                                 a.st_phys + (long long)a.mode * S * a.g.total);

@@ -480,7 +480,13 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
                                                    : (size_t)2 * W * ax.fb_pitch * 8;
   const size_t res_bytes = (size_t)16 * t.RB * ax.r_pitch * p->w;
   ax.fb_off = (int)tile_bytes;
-  size_t lds = tile_bytes + std::max(fold_bytes, res_bytes);
+  // FP32 x tiles: a second fold buffer where it fits (the unfold's result
+  // rows fit one buffer)
+  ax.nfb = p->dtype == SFRDE_F32 && axis == 0 &&
+                   tile_bytes + std::max(2 * fold_bytes, res_bytes) <= 160 * 1024
+               ? 2
+               : 1;
+  size_t lds = tile_bytes + std::max(ax.nfb * fold_bytes, res_bytes);
   lds = std::max<size_t>(lds, (size_t)threads * sizeof(double));
   if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: FFT or dense kernels
   p->lds_m[axis] = lds;
