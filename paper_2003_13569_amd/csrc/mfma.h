@@ -1672,7 +1672,9 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
   }
 }
 
-template <typename T, class XF, bool FAST>
+// NS > 0 (FAST FP32 launches of one or two species, chosen by the host): the
+// vector adjoint reaction of NS species only.
+template <typename T, class XF, bool FAST, int NS = 0>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(StageArgs<T> a, MfmaAxisDev ax) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1689,7 +1691,9 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
   for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
     const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
     xf(buf, S);
-    if constexpr (FAST && std::is_same<T, float>::value && XF::XAX)
+    if constexpr (FAST && std::is_same<T, float>::value && XF::XAX && NS > 0)
+      xadj_reaction_vec<NS>(a, buf, tile, pacc);
+    else if constexpr (FAST && std::is_same<T, float>::value && XF::XAX)
       xadj_reaction_fast(a, buf, tile, pacc);
     else
       pw_adj_reaction(a, buf, tile, pacc);
@@ -1732,8 +1736,10 @@ __device__ __forceinline__ void zadj_staged(const StageArgs<float>& a, float* bu
 }
 
 // MODE >= 0: one kernel per adjoint stage (FAST FP32 plans with L formed in
-// the kernel); MODE < 0 takes a.mode at run time.
-template <typename T, class XF, bool FAST, int MODE = -1>
+// the kernel); MODE < 0 takes a.mode at run time. THV = 1 / 0 (with MODE >=
+// 0): launches with / without the kappa/alpha partials (a.thp), chosen by the
+// host where the staged path applies; only that path is compiled.
+template <typename T, class XF, bool FAST, int MODE = -1, int THV = -1>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(StageArgs<T> a, MfmaAxisDev ax) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1755,8 +1761,12 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
       __syncthreads();
       // kappa, alpha partials of (at most, host-checked) two species
       double acc[4] = {0.0, 0.0, 0.0, 0.0};
-      const bool th = a.thp != nullptr;
-      if constexpr (MODE >= 0) {
+      const bool th = THV >= 0 ? THV == 1 : a.thp != nullptr;
+      if constexpr (MODE >= 0 && THV == 1) {
+        zadj_staged<XF, MODE, MODE <= 2>(a, buf, xf, pipe, lam_lds, acc, run);
+      } else if constexpr (MODE >= 0 && THV == 0) {
+        zadj_staged<XF, MODE, false>(a, buf, xf, pipe, lam_lds, acc, run);
+      } else if constexpr (MODE >= 0) {
         if (th)
           zadj_staged<XF, MODE, MODE <= 2>(a, buf, xf, pipe, lam_lds, acc, run);
         else
@@ -1781,6 +1791,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
       return;
     }
   }
+  if constexpr (THV >= 0) return;  // launched only where the path above applies
   __syncthreads();
   for (long long tile = run.t0; tile < run.t1; ++tile) {
     const long long next = run.next(tile);

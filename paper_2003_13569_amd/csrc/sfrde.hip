@@ -603,11 +603,18 @@ int set_lds_attrs(size_t bytes) {
                           reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, 3, true>),
                           reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, true>),
                           reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true>),
-                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 0>),
-                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 1>),
-                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 2>),
-                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 3>),
-                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, MODE_INIT>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 0, 0>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 1, 0>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 2, 0>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 3, 0>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, MODE_INIT, 0>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 0, 1>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 1, 1>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 2, 1>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, 3, 1>),
+                          reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, MODE_INIT, 1>),
+                          reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, true, 1>),
+                          reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, true, 2>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true, 1>),
@@ -1038,7 +1045,14 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
   const long long pk = prof_start(p, KC_XADJ);
   if (p->use_m[0]) {
     const dim3 grid(p->grid_m[0], p->B), block(XfX<T>::THREADS);
-    if (use_fast<T>(p, 0, {p->Pa}))
+    const bool fast = use_fast<T>(p, 0, {p->Pa});
+    if (std::is_same<T, float>::value && fast && p->S == 1)
+      hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, true, 1>), grid, block, p->lds_m[0], p->stream, a,
+                         p->mfax[0]);
+    else if (std::is_same<T, float>::value && fast && p->S == 2)
+      hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, true, 2>), grid, block, p->lds_m[0], p->stream, a,
+                         p->mfax[0]);
+    else if (fast)
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, std::is_same<T, float>::value>), grid, block,
                          p->lds_m[0], p->stream, a, p->mfax[0]);
     else
@@ -1077,12 +1091,25 @@ int launch_zadj(sfrde_plan_s* p, int mode, const StepStore<T>* st, int last) {
     const bool staged = fast && p->lfly && (p->thp_on || !p->G) && mode >= 0 && mode <= MODE_INIT;
     if constexpr (std::is_same<T, float>::value) {
       if (staged) {
-        switch (mode) {
-          case 0: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 0>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
-          case 1: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 1>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
-          case 2: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 2>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
-          case 3: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 3>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
-          default: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, MODE_INIT>), grid, block, lds, p->stream, a, p->mfax[ax]); break;
+        // the instance with or without the kappa/alpha partials
+        const MfmaAxisDev& mx = p->mfax[ax];
+        hipStream_t sm = p->stream;
+        if (p->thp_on) {
+          switch (mode) {
+            case 0: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 0, 1>), grid, block, lds, sm, a, mx); break;
+            case 1: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 1, 1>), grid, block, lds, sm, a, mx); break;
+            case 2: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 2, 1>), grid, block, lds, sm, a, mx); break;
+            case 3: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 3, 1>), grid, block, lds, sm, a, mx); break;
+            default: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, MODE_INIT, 1>), grid, block, lds, sm, a, mx); break;
+          }
+        } else {
+          switch (mode) {
+            case 0: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 0, 0>), grid, block, lds, sm, a, mx); break;
+            case 1: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 1, 0>), grid, block, lds, sm, a, mx); break;
+            case 2: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 2, 0>), grid, block, lds, sm, a, mx); break;
+            case 3: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, 3, 0>), grid, block, lds, sm, a, mx); break;
+            default: hipLaunchKernelGGL((k_zadj_m<T, XfZ<T>, true, MODE_INIT, 0>), grid, block, lds, sm, a, mx); break;
+          }
         }
         goto zadj_launched;
       }
