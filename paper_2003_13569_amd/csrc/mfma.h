@@ -859,8 +859,9 @@ __device__ __forceinline__ void xadj_reaction_fast(const StageArgs<float>& a, fl
 
 // FP64 tiles (W = 16 lines, 512 threads) moved through registers, CAP
 // vectors of two doubles per thread, when the launch allows it (g.fast, set
-// by the host for full tiles of at most two species, n a multiple of 64 up
-// to 256, 16-byte aligned fields) and the tile needs at most CAP vectors:
+// by the host for full tiles of at most two species, 16-byte aligned fields,
+// n a multiple of 64 up to 256 on strided axes and n = 64, 128 or 256 on the
+// x axis) and the tile needs at most CAP vectors:
 //   strided axes: thread t moves columns 2(t%8), +1 of rows t/8 + 64k;
 //   x axis: consecutive threads move consecutive point pairs of a line.
 template <int CAP>

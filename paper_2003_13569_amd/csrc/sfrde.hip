@@ -462,9 +462,10 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
              (long long)p->S * g.n >= 64 && g.outer % W == 0;
   else if (f32)
     g.fast = g.inner % W == 0 && g.n % 64 == 0 && g.n <= 256;
-  else  // FP64: full tiles of at most two species move through registers (TileIOF64)
+  else  // FP64: full tiles of at most two species move through registers (TileIOF64;
+        // its x-axis layout needs n = 64, 128 or 256, strided axes a multiple of 64)
     g.fast = g.n % 64 == 0 && g.n <= 256 && g.spt <= 2 &&
-             (g.inner == 1 ? g.outer % W == 0 : g.inner % W == 0);
+             (g.inner == 1 ? g.outer % W == 0 && (g.n & (g.n - 1)) == 0 : g.inner % W == 0);
   MfmaAxisDev& ax = p->mfax[axis];
   ax.hK = t.hK;
   ax.RBe = t.RBe;

@@ -96,6 +96,50 @@ def test_fp32_vector_paths_match_oracle(wl, scheme):
     assert problem.rel_err(got, ref) <= 2e-5
 
 
+# The FP64 engine moves full tiles through registers (x axes of 64, 128 or
+# 256 points; strided axes of multiples of 64, with one or both species per
+# tile); an x axis of 192 points takes its generic in-place loads.
+X192 = _wl("sch2d-neu-x192", "neumann", (64, 192), "schnakenberg", SCH, (1.5, 1.2), (0.05, 1.0),
+           0.005, "schnak_noise", (0.0, 1.0))
+F64_TILE_CASES = VEC_CASES + [X192]
+
+
+@pytest.mark.parametrize("wl", F64_TILE_CASES, ids=[c.name for c in F64_TILE_CASES])
+def test_fp64_register_tile_paths_match_oracle(wl):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 5)
+    got = run(wl, u0, 5, "f64")
+    assert problem.rel_err(got, ref) <= 1e-10
+
+
+def test_fp32_x_axis_of_192_points_matches_oracle():
+    u0 = W.initial_fields(X192)
+    ref = problem.run(X192, u0, 5)
+    assert problem.rel_err(run(X192, u0, 5, "f32"), ref) <= 2e-5
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-6)])
+def test_fields_off_16_byte_boundaries_match_aligned_ones(dtype, tol):
+    """A caller's field 8 (FP64) or 4 (FP32) bytes past a 16-byte boundary:
+    the launches that read or write it take the element-wise tile paths
+    instead of the 16-byte vector ones, with the same arithmetic."""
+    wl = VEC_CASES[1]  # every axis on the vector / register tile paths
+    u0 = W.initial_fields(wl)
+    p = plan_for(wl, dtype, None)
+    a = torch.tensor(u0, dtype=TD[dtype], device="cuda")
+    big = torch.zeros(a.numel() + 1, dtype=TD[dtype], device="cuda")
+    b = big[1:].view(a.shape)
+    b.copy_(a)
+    assert b.data_ptr() % 16 != 0
+    p.integrate(a, 3, 0.0)
+    p.integrate(b, 3, 0.0)
+    torch.cuda.synchronize()
+    got, ref = b.double().cpu().numpy(), a.double().cpu().numpy()
+    p.close()
+    assert problem.rel_err(got, ref) <= tol
+    assert problem.rel_err(ref, problem.run(wl, u0, 3)) <= (1e-10 if dtype == "f64" else 2e-5)
+
+
 # Axes the matrix-core engine and the FFT kernels do not take (n > 256, and
 # periodic n >= 256 that is not 256, 512 or 1024) run the dense LDS kernels,
 # with tiles narrowed to fill the device.
