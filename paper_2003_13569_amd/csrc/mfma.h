@@ -353,9 +353,10 @@ struct MfmaXfF32 {
     }
   }
 
-  // DCT-I / DST-I transform of one species' tile x with the results written
-  // straight to global memory: row k of the tile to g + k inner (16 lanes
-  // write 64 contiguous bytes). The tile in LDS is left as it was.
+  // DCT-I / DST-I transform of one species' strided tile x with the results
+  // written straight to global memory: row k of the tile to g + k inner (16
+  // lanes write 64 contiguous bytes; x tiles, whose lines are n apart, never
+  // take this path). The tile in LDS is left as it was.
   __device__ __forceinline__ void to_global(const float* x, float* g, long long inner) {
     fold(x);
     __syncthreads();
@@ -941,11 +942,12 @@ struct TileIOF64 {
   }
 };
 
-// Register prefetch of a tile. FAST kernels (chosen by the host when every
-// tile is full, the shapes fit the layouts above and the pointers are
-// 16-byte aligned) move tiles with TileIO only; the others with the generic
-// paths, loading in place. Keeping the two apart keeps the compiler's wait
-// counts exact on the fast path.
+// Register prefetch of a tile. FAST FP32 kernels (chosen by the host when
+// every tile is full, the shapes fit the layouts above and the pointers are
+// 16-byte aligned) move tiles with TileIO only; the other FP32 kernels with
+// the generic paths, loading in place. Keeping the two apart keeps the
+// compiler's wait counts exact on the fast path. FP64 kernels decide per
+// launch (the specialisation below).
 template <typename T, int W, bool FAST, bool XAX>
 struct TilePipe {
   using IO = typename std::conditional<XAX && std::is_same<T, float>::value, XTileIO<W>,
@@ -1811,8 +1813,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
 // One transform along one axis, src -> dst (may alias), optional Neumann
 // point weights before (divide) or after (multiply).
 // PATH (FAST FP32 launches without point weights, chosen by the host): 1 =
-// results straight to global memory (DCT-I / DST-I on one-species tiles),
-// 2 = through the tile; only that path is compiled. 0: every path.
+// results straight to global memory (DCT-I / DST-I on one-species strided
+// tiles), 2 = through the tile; only that path is compiled. 0: every path.
 template <typename T, class XF, bool FAST, int PATH = 0>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(SingleArgs<T> a, MfmaAxisDev ax) {
   to_member(a);
@@ -1833,7 +1835,9 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
       pa.commit(g, blockIdx.x, a.src, buf);
       __syncthreads();
       // results of DCT-I / DST-I transforms go straight to global memory
-      const bool direct = PATH == 1 || (PATH == 0 && ax.direct != 0 && g.spt == 1);
+      // (x tiles hold their points along the rows: never straight to global memory)
+      const bool direct =
+          PATH == 1 || (PATH == 0 && !XF::XAX && ax.direct != 0 && g.spt == 1 && g.inner > 1);
       for (long long tile = blockIdx.x; tile < g.ntiles; tile += 2 * G) {
         pa.issue(g, nxt(tile + 2 * G), a.src);
         if (direct) {

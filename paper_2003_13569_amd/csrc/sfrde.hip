@@ -618,7 +618,6 @@ int set_lds_attrs(size_t bytes) {
                           reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, true, 2>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true>),
-                          reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true, 1>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true, 1>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true, 2>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true, 2>),
@@ -716,15 +715,14 @@ int launch_single(sfrde_plan_s* p, int axis, const void* src, void* dst, int pre
     // fast launches without point weights: the kernel holding only the
     // tile path that runs
     const bool plain = fast && !a.pre_divide_w && !a.post_multiply_w;
-    const bool to_glob = p->mfax[axis].direct != 0 && a.g.spt == 1;
+    // results straight to global memory: DCT-I / DST-I on one-species
+    // strided tiles (rows inner apart, columns contiguous)
+    const bool to_glob = p->mfax[axis].direct != 0 && a.g.spt == 1 && a.g.inner > 1;
     if (axis == 0) {
       const dim3 block(XfX<T>::THREADS);
       if constexpr (std::is_same<T, float>::value)
         if (fast) {
-          if (plain && to_glob)
-            hipLaunchKernelGGL((k_single_m<T, XfX<T>, true, 1>), grid, block, lds, p->stream, a,
-                               p->mfax[axis]);
-          else if (plain)
+          if (plain)  // x tiles: through the tile
             hipLaunchKernelGGL((k_single_m<T, XfX<T>, true, 2>), grid, block, lds, p->stream, a,
                                p->mfax[axis]);
           else

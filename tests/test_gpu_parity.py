@@ -118,6 +118,25 @@ def test_fp32_x_axis_of_192_points_matches_oracle():
     assert problem.rel_err(run(X192, u0, 5, "f32"), ref) <= 2e-5
 
 
+# One species on x axes the vector paths take (64, 128, 256 points,
+# non-periodic): the x-axis transforms before and after the steps run on
+# tiles of that one species.
+ONE_SPECIES_CASES = [
+    _wl("lin1-neu-x256", "neumann", (32, 256), "linear", (-0.5,), (1.6,), (1e-3,), 0.5,
+        "normal", (0.0, 1.0)),
+    _wl("lin1-dir-x128", "dirichlet", (8, 32, 128), "linear", (0.25,), (1.8,), (2e-3,), 0.2,
+        "normal", (0.0, 1.0)),
+]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+@pytest.mark.parametrize("wl", ONE_SPECIES_CASES, ids=[c.name for c in ONE_SPECIES_CASES])
+def test_one_species_on_vector_x_axes_matches_oracle(wl, dtype, tol):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 5)
+    assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
+
+
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-6)])
 def test_fields_off_16_byte_boundaries_match_aligned_ones(dtype, tol):
     """A caller's field 8 (FP64) or 4 (FP32) bytes past a 16-byte boundary:
