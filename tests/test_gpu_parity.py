@@ -137,6 +137,28 @@ def test_one_species_on_vector_x_axes_matches_oracle(wl, dtype, tol):
     assert problem.rel_err(run(wl, u0, 5, dtype), ref) <= tol
 
 
+# The engine's paths are chosen by precision, species count, boundary
+# condition and axis lengths: the linear reaction (any species count) on a
+# 2D grid with x = 128 and y = 64 points and a 3D one with 64-point x and y
+# axes, for one to three species and every boundary condition.
+def _lin(S, bc, shape):
+    return _wl(f"lin{S}-{bc[:3]}-{'x'.join(map(str, shape))}", bc, shape, "linear",
+               (-0.5, 0.25, -1.0)[:S], (1.6, 1.8, 1.2)[:S], (1e-3, 2e-3, 5e-4)[:S], 0.3,
+               "normal", (0.0, 1.0))
+
+
+PATH_MATRIX = [_lin(S, bc, shape) for shape in ((64, 128), (32, 64, 64))
+               for bc in ("neumann", "dirichlet", "periodic") for S in (1, 2, 3)]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 2e-5)])
+@pytest.mark.parametrize("wl", PATH_MATRIX, ids=[c.name for c in PATH_MATRIX])
+def test_species_count_and_boundary_matrix_matches_oracle(wl, dtype, tol):
+    u0 = W.initial_fields(wl)
+    ref = problem.run(wl, u0, 4)
+    assert problem.rel_err(run(wl, u0, 4, dtype), ref) <= tol
+
+
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 1e-6)])
 def test_fields_off_16_byte_boundaries_match_aligned_ones(dtype, tol):
     """A caller's field 8 (FP64) or 4 (FP32) bytes past a 16-byte boundary:
