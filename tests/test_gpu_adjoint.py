@@ -8,7 +8,7 @@ import workloads as W
 from oracle import problem
 from paper_2003_13569_amd.torch_api import SFRDEFunction
 from tests.gpu_util import TD, plan_for
-from tests.test_gpu_parity import CASES, DENSE_CASES, FFT_CASES, VEC_CASES
+from tests.test_gpu_parity import CASES, DENSE_CASES, FFT_CASES, PATH_MATRIX, VEC_CASES
 
 pytestmark = pytest.mark.gpu
 
@@ -72,6 +72,26 @@ def test_fp32_adjoint_vector_paths_match_oracle(wl):
     for key in ("kappa", "alpha", "params"):
         r, g = ref[key], got[key]
         assert np.max(np.abs(g - r)) <= 1e-3 * max(np.max(np.abs(r)), 1e-300), (key, g, r)
+
+
+# The adjoint's instances by species count (one, two, three species) and
+# boundary condition on the 2D grid whose axes take the vector paths, in
+# both precisions.
+ADJ_MATRIX = [wl for wl in PATH_MATRIX if len(wl.shape) == 2]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("wl", ADJ_MATRIX, ids=[c.name for c in ADJ_MATRIX])
+def test_adjoint_species_count_and_boundary_matrix_matches_oracle(wl, dtype):
+    u0 = W.initial_fields(wl)
+    wbar = np.random.default_rng(14).standard_normal(u0.shape)
+    ref = problem.gradients(wl, u0, M, wbar)
+    got = _gpu_grads(wl, u0, wbar, dtype)
+    t_u, t_p = (1e-10, 1e-10) if dtype == "f64" else (1e-4, 1e-3)
+    assert _rel(got["u0"], ref["u0"]) <= t_u
+    for key in ("kappa", "alpha", "params"):
+        r, g = ref[key], got[key]
+        assert np.max(np.abs(g - r)) <= t_p * max(np.max(np.abs(r)), 1e-300), (key, g, r)
 
 
 def test_checkpoint_spacing_does_not_change_gradients():
