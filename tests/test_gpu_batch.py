@@ -54,19 +54,22 @@ def test_batch_members_match_oracle(wl, dtype, tol):
         assert problem.rel_err(got[b], ref) <= tol, (b, problem.rel_err(got[b], ref))
 
 
-@pytest.mark.parametrize("wl", VEC_CASES[:2], ids=[c.name for c in VEC_CASES[:2]])
-def test_batch_fp32_vector_paths_match_oracle(wl):
+@pytest.mark.parametrize("dtype,tol", [("f32", 2e-5), ("f64", 1e-10)])
+@pytest.mark.parametrize("wl", VEC_CASES[:3], ids=[c.name for c in VEC_CASES[:3]])
+def test_batch_vector_paths_match_oracle(wl, dtype, tol):
+    """Members on the FP32 vector paths and the FP64 register tiles (each
+    member's fields at its own offset)."""
     members = _members(wl, 2)
     u0 = np.stack([W.initial_fields(m) for m in members])
-    p = _batch_plan(members, "f32")
-    u = torch.tensor(u0, dtype=torch.float32, device="cuda")
+    p = _batch_plan(members, dtype)
+    u = torch.tensor(u0, dtype=TD[dtype], device="cuda")
     p.integrate(u, 3, 0.0)
     torch.cuda.synchronize()
     got = u.double().cpu().numpy()
     p.close()
     for b, m in enumerate(members):
         ref = problem.run(m, u0[b], 3)
-        assert problem.rel_err(got[b], ref) <= 2e-5
+        assert problem.rel_err(got[b], ref) <= tol
 
 
 def test_batch_adjoint_matches_oracle_per_member():

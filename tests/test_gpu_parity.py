@@ -104,8 +104,10 @@ X192 = _wl("sch2d-neu-x192", "neumann", (64, 192), "schnakenberg", SCH, (1.5, 1.
 F64_TILE_CASES = VEC_CASES + [X192]
 
 
+@pytest.mark.parametrize("scheme", ["p13", "exp"])
 @pytest.mark.parametrize("wl", F64_TILE_CASES, ids=[c.name for c in F64_TILE_CASES])
-def test_fp64_register_tile_paths_match_oracle(wl):
+def test_fp64_register_tile_paths_match_oracle(wl, scheme):
+    wl = wl.replace(scheme=scheme)
     u0 = W.initial_fields(wl)
     ref = problem.run(wl, u0, 5)
     got = run(wl, u0, 5, "f64")
