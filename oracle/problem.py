@@ -7,11 +7,12 @@ from . import reactions
 from .separable import SeparableScheme
 
 
-def scheme(wl, alpha=None, kappa=None, scheme_name=None):
+def scheme(wl, alpha=None, kappa=None, scheme_name=None, periodic_basis="lapack"):
     return SeparableScheme(wl.bc, wl.shape, wl.h,
                            wl.alpha if alpha is None else alpha,
                            wl.kappa if kappa is None else kappa,
-                           wl.dt, wl.scheme if scheme_name is None else scheme_name)
+                           wl.dt, wl.scheme if scheme_name is None else scheme_name,
+                           periodic_basis)
 
 
 def nonlinearity(wl, params=None):
@@ -26,9 +27,9 @@ def run(wl, U0, nsteps=None, t0=0.0, **kw):
     return sch.integrate(U0, n, nonlinearity(wl), t0)
 
 
-def gradients(wl, U0, nsteps, grad_uT, t0=0.0):
+def gradients(wl, U0, nsteps, grad_uT, t0=0.0, **kw):
     """Discrete adjoint: d<grad_uT, u_T>/d(u0, kappa, alpha, params)."""
-    sch = scheme(wl)
+    sch = scheme(wl, **kw)
     kind, p = wl.reaction, wl.params
     jacT = lambda U, G, t: reactions.jacT(kind, p, U, G)
     dpar = lambda U, G, t: reactions.dparams(kind, p, U, G)

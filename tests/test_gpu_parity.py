@@ -219,6 +219,11 @@ FFT_CASES = [
         (0.05, 1.0), 0.01, "schnak_noise", (0.0, 1.0)),
     _wl("lin3-per-fft-x", "periodic", (5, 512), "linear", (-0.5, 0.25, -1.0), (1.6, 1.8, 1.2),
         (1e-3, 2e-3, 5e-4), 0.5, "normal", (0.0, 1.0)),
+    # one species: x tiles of two lines, strided tiles of four
+    _wl("lin1-per-fft-x", "periodic", (6, 1024), "linear", (-0.5,), (1.6,), (1e-3,), 0.5,
+        "normal", (0.0, 1.0)),
+    _wl("lin1-per-fft-y", "periodic", (256, 12), "linear", (0.25,), (1.8,), (2e-3,), 0.5,
+        "normal", (0.0, 1.0)),
 ]
 
 
