@@ -80,9 +80,11 @@ def test_fp32_adjoint_vector_paths_match_oracle(wl):
 ADJ_MATRIX = [wl for wl in PATH_MATRIX if len(wl.shape) == 2]
 
 
+@pytest.mark.parametrize("scheme", ["p13", "exp"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("wl", ADJ_MATRIX, ids=[c.name for c in ADJ_MATRIX])
-def test_adjoint_species_count_and_boundary_matrix_matches_oracle(wl, dtype):
+def test_adjoint_species_count_and_boundary_matrix_matches_oracle(wl, dtype, scheme):
+    wl = wl.replace(scheme=scheme)
     u0 = W.initial_fields(wl)
     wbar = np.random.default_rng(14).standard_normal(u0.shape)
     ref = problem.gradients(wl, u0, M, wbar)
