@@ -352,17 +352,20 @@ def test_zero_steps_leave_state_untouched():
     p.close()
 
 
-def test_runs_are_bitwise_deterministic():
-    wl = CASES[4]
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("wl", [CASES[4], VEC_CASES[1], FFT_CASES[1]],
+                         ids=["small", "vector-paths", "fft"])
+def test_runs_are_bitwise_deterministic(wl, dtype):
     u0 = W.initial_fields(wl)
-    a = run(wl, u0, 6, "f32")
-    b = run(wl, u0, 6, "f32")
+    a = run(wl, u0, 6, dtype)
+    b = run(wl, u0, 6, dtype)
     assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_resume_from_checkpoint_is_bitwise_identical(dtype):
-    wl = CASES[2]
+@pytest.mark.parametrize("wl", [CASES[2], VEC_CASES[1], FFT_CASES[1]],
+                         ids=["small", "vector-paths", "fft"])
+def test_resume_from_checkpoint_is_bitwise_identical(dtype, wl):
     u0 = W.initial_fields(wl)
     p = plan_for(wl, dtype)
     u = torch.tensor(u0, dtype=TD[dtype], device="cuda")
@@ -492,20 +495,26 @@ def test_one_dimensional_adjoint_matches_oracle(wl):
         assert np.max(np.abs(np.array(got) - r)) <= 1e-10 * max(np.max(np.abs(r)), 1e-300), key
 
 
-def test_single_steps_match_integrate():
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-12), ("f32", 2e-6)])
+@pytest.mark.parametrize("wl", [CASES[1], VEC_CASES[1], FFT_CASES[1]],
+                         ids=["small", "vector-paths", "fft"])
+def test_single_steps_match_integrate(wl, dtype, tol):
     # sfrde_step is one step from physical data (forward transforms of the
     # state each call): k calls agree with one k-step integrate to rounding,
     # and a step at time t equals a one-step integrate from t0 = t.
-    wl = CASES[1]
     u0 = W.initial_fields(wl)
-    p = plan_for(wl, "f64")
-    a = torch.tensor(u0, dtype=torch.float64, device="cuda")
+    p = plan_for(wl, dtype)
+    a = torch.tensor(u0, dtype=TD[dtype], device="cuda")
     b = a.clone()
     for k in range(4):
         p.step(a, k * wl.dt)
     p.integrate(b, 4, 0.0)
     torch.cuda.synchronize()
-    assert problem.rel_err(a.cpu().numpy(), b.cpu().numpy()) <= 1e-12
+    assert problem.rel_err(a.double().cpu().numpy(), b.double().cpu().numpy()) <= tol
+    p.close()
+
+
+def test_single_step_at_time_t_is_a_one_step_integrate_from_t():
     h = 1.0 / 20
     pm = Plan((20, 20), "periodic", (h, h), (1.5,), (1.0,), 0.1 * h, "huxley_mms", (), "f64")
     x = torch.zeros((1, 20, 20), dtype=torch.float64, device="cuda")
@@ -515,7 +524,6 @@ def test_single_steps_match_integrate():
     torch.cuda.synchronize()
     assert torch.equal(x, y)
     pm.close()
-    p.close()
 
 
 def test_checkpoint_and_workspace_sizes():
