@@ -48,6 +48,7 @@ struct Geom {
   long long inner;  // stride of the axis (1 for x)
   long long outer;  // lines (inner == 1) or outer blocks of n*inner
   long long tpo;    // tiles per outer block (inner > 1)
+  int tposh;        // log2(tpo) when tpo is a power of two, else -1
   long long ntiles;
   long long total;  // points per species
 };
@@ -60,6 +61,25 @@ struct TileRef {
   int rs, cs;
 };
 
+// Outer block o of a strided-axis tile and the tile's index r within it: a
+// shift when the tiles per outer block are a power of two, else a 32-bit
+// division while the tile count allows (the 64-bit one costs several times
+// as many instructions, each tile several times).
+__device__ __forceinline__ void split_tile(const Geom& g, long long tile, long long& o,
+                                           long long& r) {
+  if (g.tposh >= 0) {
+    o = tile >> g.tposh;
+    r = tile & ((1LL << g.tposh) - 1);
+  } else if (g.ntiles <= 0x7fffffffLL) {
+    const unsigned q = (unsigned)tile / (unsigned)g.tpo;
+    o = q;
+    r = (long long)((unsigned)tile - q * (unsigned)g.tpo);
+  } else {
+    o = tile / g.tpo;
+    r = tile - o * g.tpo;
+  }
+}
+
 __device__ __forceinline__ TileRef tile_ref(const Geom& g, long long tile) {
   TileRef t;
   if (g.inner == 1) {
@@ -70,8 +90,9 @@ __device__ __forceinline__ TileRef tile_ref(const Geom& g, long long tile) {
     t.rs = 1;
     t.cs = g.n;
   } else {
-    const long long o = tile / g.tpo;
-    const long long i0 = (tile - o * g.tpo) * g.W;
+    long long o, r;
+    split_tile(g, tile, o, r);
+    const long long i0 = r * g.W;
     t.base = o * (long long)g.n * g.inner + i0;
     const long long left = g.inner - i0;
     t.wvalid = left < g.W ? (int)left : g.W;

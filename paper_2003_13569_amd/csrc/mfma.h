@@ -1044,9 +1044,10 @@ __device__ __forceinline__ void combine_pre(const StageArgs<float>& a, float* bu
   float lxy[4], kt = 0.f, ha = 0.f;
   const float* lz = lam_lds;
   if (a.lfly) {
-    const long long o = tile / g.tpo;
+    long long o, rt;
+    split_tile(g, tile, o, rt);
     const int s = (int)o;
-    const int ib = (int)(tile - o * g.tpo) * 32 + w4;
+    const int ib = (int)rt * 32 + w4;
     const int n0 = (int)a.n0, n1 = (int)a.n1;
     const bool three = a.n2 > 1;
     lz = lam_lds + n0 + (three ? n1 : 0);
@@ -1197,9 +1198,10 @@ __device__ __forceinline__ void zadj_tile32(const StageArgs<float>& a, float* bu
   const long long inner = g.inner;
   const long long i0 = tr.base + r0 * inner + w4;
   const float cs = a.cs, tau = a.tau;
-  const long long o = tile / g.tpo;
+  long long o, rt;
+  split_tile(g, tile, o, rt);
   const int s = (int)o;
-  const int ib = (int)(tile - o * g.tpo) * 32 + w4;
+  const int ib = (int)rt * 32 + w4;
   const int n0 = (int)a.n0, n1 = (int)a.n1;
   const bool three = a.n2 > 1;
   const float* lz = lam_lds + n0 + (three ? n1 : 0);
@@ -1528,15 +1530,15 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
   T* buf = reinterpret_cast<T*>(smem_raw);
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const int S = a.g.spt;
-  const long long last = a.g.ntiles - 1;
+  const int last = (int)(a.g.ntiles - 1);
   bool bad = false;
   if constexpr (FAST && std::is_same<T, float>::value) {
     if (RK >= 0 || (ax.direct && S == 2)) {
       // inverse-x folded straight from registers: no LDS staging of the input
       XFoldLoads rl;
       rl.issue(a.g, blockIdx.x, a.P);
-      for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-        const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+      for (int tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
+        const int next = tile + gridDim.x < last ? tile + gridDim.x : last;
         xf.fold_regs(rl.v[0]);
         __syncthreads();
         xf.mfma_write(buf, !xf.two_buffers());
@@ -1566,8 +1568,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
   pipe.issue(a.g, blockIdx.x, a.P);
   pipe.commit(a.g, blockIdx.x, a.P, buf);
   __syncthreads();
-  for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+  for (int tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
+    const int next = tile + gridDim.x < last ? tile + gridDim.x : last;
     pipe.issue(a.g, next, a.P);
     xf(buf, S);
     if constexpr (FAST && std::is_same<T, float>::value) {
@@ -1597,13 +1599,11 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
 // whole field rather than in one slab of it, which the strided rows of a
 // last-axis tile read at a higher HBM rate.
 struct TileRun {
-  long long t0, t1;
+  int t0, t1;  // tile counts of the engine's launches stay below 2^31 (host-checked)
   __device__ __forceinline__ explicit TileRun(long long ntiles)
-      : t0((long long)blockIdx.x * ntiles / gridDim.x),
-        t1(((long long)blockIdx.x + 1) * ntiles / gridDim.x) {}
-  __device__ __forceinline__ long long next(long long tile) const {
-    return tile + 1 < t1 ? tile + 1 : t1 - 1;
-  }
+      : t0((int)((long long)blockIdx.x * ntiles / gridDim.x)),
+        t1((int)(((long long)blockIdx.x + 1) * ntiles / gridDim.x)) {}
+  __device__ __forceinline__ int next(int tile) const { return tile + 1 < t1 ? tile + 1 : t1 - 1; }
 };
 
 // MODE >= 0 (FAST FP32 plans, forward stages; last axes of 64, 128, 192 or
@@ -1634,8 +1634,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
     ld.issue(a, run.t0);
     pipe.commit(a.g, run.t0, src, buf);
     __syncthreads();
-    for (long long tile = run.t0; tile < run.t1; ++tile) {
-      const long long next = run.next(tile);
+    for (int tile = run.t0; tile < run.t1; ++tile) {
+      const int next = run.next(tile);
       pipe.issue(a.g, next, src);
       xf(buf, 1);
       combine_pre<MODE>(a, buf, tile, ld, lam_lds);
@@ -1657,8 +1657,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
     pipe.issue(a.g, run.t0, src);
     pipe.commit(a.g, run.t0, src, buf);
     __syncthreads();
-    for (long long tile = run.t0; tile < run.t1; ++tile) {
-      const long long next = run.next(tile);
+    for (int tile = run.t0; tile < run.t1; ++tile) {
+      const int next = run.next(tile);
       if (!a.src) xf(buf, S);
       if constexpr (MODE >= 0 && MODE <= 3 && !std::is_same<T, float>::value)
         combine_mode<T, MODE>(a, buf, tile);
@@ -1686,13 +1686,13 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
   double pacc[RXN_NP_MAX];
   for (int k = 0; k < RXN_NP_MAX; ++k) pacc[k] = 0.0;
   const int S = a.g.spt;
-  const long long last = a.g.ntiles - 1;
+  const int last = (int)(a.g.ntiles - 1);
   TilePipe<T, XF::W, FAST, true> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
   pipe.commit(a.g, blockIdx.x, a.P, buf);
   __syncthreads();
-  for (long long tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
-    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+  for (int tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
+    const int next = tile + gridDim.x < last ? tile + gridDim.x : last;
     xf(buf, S);
     if constexpr (FAST && std::is_same<T, float>::value && XF::XAX && NS > 0)
       xadj_reaction_vec<NS>(a, buf, tile, pacc);
@@ -1722,8 +1722,8 @@ __device__ __forceinline__ void zadj_staged(const StageArgs<float>& a, float* bu
   // with the kappa/alpha terms, the stored stage arrays are loaded after the
   // forward transform (fewer registers live across it)
   constexpr int NE = TH ? 2 : AdjLoads<MODE, TH>::NQ;
-  for (long long tile = run.t0; tile < run.t1; ++tile) {
-    const long long next = run.next(tile);
+  for (int tile = run.t0; tile < run.t1; ++tile) {
+    const int next = run.next(tile);
     ld.template issue<0, NE>(a, tile);
     xf(buf, 1);
     ld.template issue<NE, AdjLoads<MODE, TH>::NQ>(a, tile);
@@ -1775,8 +1775,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
         else
           zadj_staged<XF, MODE, false>(a, buf, xf, pipe, lam_lds, acc, run);
       } else
-      for (long long tile = run.t0; tile < run.t1; ++tile) {
-        const long long next = run.next(tile);
+      for (int tile = run.t0; tile < run.t1; ++tile) {
+        const int next = run.next(tile);
         xf(buf, 1);
         if (th)
           zadj_vec<true>(a, buf, tile, lam_lds, acc);
@@ -1796,8 +1796,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zadj_m(St
   }
   if constexpr (THV >= 0) return;  // launched only where the path above applies
   __syncthreads();
-  for (long long tile = run.t0; tile < run.t1; ++tile) {
-    const long long next = run.next(tile);
+  for (int tile = run.t0; tile < run.t1; ++tile) {
+    const int next = run.next(tile);
     xf(buf, S);
     pw_adj_combine(a, buf, tile);
     __syncthreads();
@@ -1823,7 +1823,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
   XF xf(&a.g, &ax, reinterpret_cast<T*>(smem_raw + ax.fb_off));
   const Geom& g = a.g;
   const int ne = g.n * g.W;
-  const long long last = g.ntiles - 1;
+  const int last = (int)(g.ntiles - 1);
   if constexpr (FAST && std::is_same<T, float>::value) {
     if (PATH != 0 || (!a.pre_divide_w && !a.post_multiply_w)) {
       // two tiles in flight: pipes A and B alternate
@@ -1838,7 +1838,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
       // (x tiles hold their points along the rows: never straight to global memory)
       const bool direct =
           PATH == 1 || (PATH == 0 && !XF::XAX && ax.direct != 0 && g.spt == 1 && g.inner > 1);
-      for (long long tile = blockIdx.x; tile < g.ntiles; tile += 2 * G) {
+      for (int tile = blockIdx.x; tile < g.ntiles; tile += 2 * G) {
         pa.issue(g, nxt(tile + 2 * G), a.src);
         if (direct) {
           xf.to_global(buf, a.dst + tile_ref(g, tile).base, g.inner);
@@ -1869,8 +1869,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_single_m(
   pipe.issue(g, blockIdx.x, a.src);
   pipe.commit(g, blockIdx.x, a.src, buf);
   __syncthreads();
-  for (long long tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
-    const long long next = tile + gridDim.x < last ? tile + gridDim.x : last;
+  for (int tile = blockIdx.x; tile < g.ntiles; tile += gridDim.x) {
+    const int next = tile + gridDim.x < last ? tile + gridDim.x : last;
     pipe.issue(g, next, a.src);
     const TileRef tr = tile_ref(g, tile);
     if (a.pre_divide_w) {

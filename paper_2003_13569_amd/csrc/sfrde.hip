@@ -280,6 +280,14 @@ double axis_inverse_scale(int bc, long long n) {
   return 2.0 / double(n - 1);
 }
 
+// log2(x) for a power of two x >= 1, else -1.
+int pow2_shift(long long x) {
+  if (x < 1 || (x & (x - 1)) != 0) return -1;
+  int k = 0;
+  while ((1LL << k) < x) ++k;
+  return k;
+}
+
 long long pow2_floor(long long x) {
   long long p = 1;
   while (p * 2 <= x) p *= 2;
@@ -316,10 +324,12 @@ void make_geom(sfrde_plan_s* p, int axis, long long min_tiles = 0) {
   if (inner == 1) {
     g.outer = p->total / n;
     g.tpo = 1;
+    g.tposh = 0;
     g.ntiles = (g.outer + W - 1) / W;
   } else {
     g.outer = p->total / (n * inner);
     g.tpo = (inner + W - 1) / W;
+    g.tposh = pow2_shift(g.tpo);
     g.ntiles = g.outer * g.tpo;
   }
   size_t tile = (size_t)p->S * n * g.pitch * p->w;
@@ -440,6 +450,7 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   while ((1 << g.wshift) < g.W) ++g.wshift;
   if (g.inner == 1) {
     g.tpo = 1;
+    g.tposh = 0;
     g.ntiles = (g.outer + W - 1) / W;
   } else {
     // Tiles along strided axes hold one species (the species index becomes
@@ -454,6 +465,7 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
       g.spt = 1;
     }
     g.tpo = (g.inner + W - 1) / W;
+    g.tposh = pow2_shift(g.tpo);
     g.ntiles = g.outer * g.tpo;
   }
   // vector tile paths of the FP32 engine (their thread layouts assume these)
@@ -490,6 +502,7 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   size_t lds = tile_bytes + std::max(ax.nfb * fold_bytes, res_bytes);
   lds = std::max<size_t>(lds, (size_t)threads * sizeof(double));
   if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: FFT or dense kernels
+  if (g.ntiles > 0x7fffffffLL) return SFRDE_OK;  // the engine's tile indices are 32-bit
   p->lds_m[axis] = lds;
   // persistent grid: as many blocks as fit on the CUs at once
   const long long per_cu = 1;
@@ -546,12 +559,14 @@ int setup_fft_axis(sfrde_plan_s* p, int axis) {
     g.spt = p->S;
     g.W = p->S <= 2 ? 2 : 1;
     g.tpo = 1;
+    g.tposh = 0;
     g.ntiles = (g.outer + g.W - 1) / g.W;
   } else {
     g.outer *= p->S;  // one species per tile: the species joins the outer index
     g.spt = 1;
     g.W = 4;
     g.tpo = (g.inner + g.W - 1) / g.W;
+    g.tposh = pow2_shift(g.tpo);
     g.ntiles = g.outer * g.tpo;
   }
   g.pitch = g.W | 1;  // odd: a line's elements fall in distinct LDS banks
