@@ -75,9 +75,10 @@ def test_fp32_adjoint_vector_paths_match_oracle(wl):
 
 
 # The adjoint's instances by species count (one, two, three species) and
-# boundary condition on the 2D grid whose axes take the vector paths, in
-# both precisions.
-ADJ_MATRIX = [wl for wl in PATH_MATRIX if len(wl.shape) == 2]
+# boundary condition on the 2D grid whose axes take the vector paths and on
+# the 1D grids, in both precisions (the periodic references in the exact
+# circulant basis).
+ADJ_MATRIX = [wl for wl in PATH_MATRIX if len(wl.shape) != 3]
 
 
 @pytest.mark.parametrize("scheme", ["p13", "exp"])
@@ -87,7 +88,7 @@ def test_adjoint_species_count_and_boundary_matrix_matches_oracle(wl, dtype, sch
     wl = wl.replace(scheme=scheme)
     u0 = W.initial_fields(wl)
     wbar = np.random.default_rng(14).standard_normal(u0.shape)
-    ref = problem.gradients(wl, u0, M, wbar)
+    ref = problem.gradients(wl, u0, M, wbar, periodic_basis="hartley")
     got = _gpu_grads(wl, u0, wbar, dtype)
     t_u, t_p = (1e-10, 1e-10) if dtype == "f64" else (1e-4, 1e-3)
     assert _rel(got["u0"], ref["u0"]) <= t_u

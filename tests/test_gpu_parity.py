@@ -141,15 +141,17 @@ def test_one_species_on_vector_x_axes_matches_oracle(wl, dtype, tol):
 
 # The engine's paths are chosen by precision, species count, boundary
 # condition and axis lengths: the linear reaction (any species count) on a
-# 2D grid with x = 128 and y = 64 points and a 3D one with 64-point x and y
-# axes, for one to three species and every boundary condition.
+# 2D grid with x = 128 and y = 64 points, a 3D one with 64-point x and y
+# axes, and 1D grids of 256 points (matrix cores) and 1024 (FFT for the
+# periodic one, dense kernels otherwise), for one to three species and every
+# boundary condition.
 def _lin(S, bc, shape):
     return _wl(f"lin{S}-{bc[:3]}-{'x'.join(map(str, shape))}", bc, shape, "linear",
                (-0.5, 0.25, -1.0)[:S], (1.6, 1.8, 1.2)[:S], (1e-3, 2e-3, 5e-4)[:S], 0.3,
                "normal", (0.0, 1.0))
 
 
-PATH_MATRIX = [_lin(S, bc, shape) for shape in ((64, 128), (32, 64, 64))
+PATH_MATRIX = [_lin(S, bc, shape) for shape in ((64, 128), (32, 64, 64), (256,), (1024,))
                for bc in ("neumann", "dirichlet", "periodic") for S in (1, 2, 3)]
 
 
