@@ -5,6 +5,8 @@ FP64 results must agree with the oracle to 1e-10 and FP32 results to 2e-5
 number of steps. Grids are small enough for the oracle but span several tiles
 with ragged tails.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -21,6 +23,14 @@ FHN = (0.1, 0.01, 0.5, 1.0, 0.0)
 GS = (0.04, 0.06)
 SCH = (1.0, 0.1305, 0.7695)
 GM = (0.1, 1.0, 1.0, 1.0, 1.0)
+
+
+@functools.lru_cache(maxsize=32)
+def oracle_run(wl, nsteps):
+    """The oracle's fields after nsteps from the workload's initial fields
+    (several tests share a reference; the exponential scheme's coefficients
+    on 10^5-10^6 modes take tens of seconds)."""
+    return problem.run(wl, W.initial_fields(wl), nsteps)
 
 
 def _wl(name, bc, shape, reaction, params, alpha, kappa, dt, init, domain, scheme="p13"):
@@ -91,7 +101,7 @@ def test_fp32_matches_oracle(wl):
 def test_fp32_vector_paths_match_oracle(wl, scheme):
     wl = wl.replace(scheme=scheme)
     u0 = W.initial_fields(wl)
-    ref = problem.run(wl, u0, 5)
+    ref = oracle_run(wl, 5)
     got = run(wl, u0, 5, "f32")
     assert problem.rel_err(got, ref) <= 2e-5
 
@@ -109,7 +119,7 @@ F64_TILE_CASES = VEC_CASES + [X192]
 def test_fp64_register_tile_paths_match_oracle(wl, scheme):
     wl = wl.replace(scheme=scheme)
     u0 = W.initial_fields(wl)
-    ref = problem.run(wl, u0, 5)
+    ref = oracle_run(wl, 5)
     got = run(wl, u0, 5, "f64")
     assert problem.rel_err(got, ref) <= 1e-10
 
