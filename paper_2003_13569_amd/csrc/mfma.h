@@ -442,7 +442,7 @@ struct MfmaXfF64 {
   static constexpr int W = 16;
   static constexpr int THREADS = 512;
   static constexpr int MIN_WAVES_PER_EU = 2;  // one block per CU, 256 registers per lane
-  static constexpr bool XAX = false;          // generic tile paths on every axis
+  static constexpr bool XAX = false;          // one engine for every axis (tiles: TileIOF64 or generic)
   static constexpr int FOLD_E = 4;            // fold entries per work item
   const Geom* g;
   const MfmaAxisDev* ax;
@@ -1599,7 +1599,7 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xstage_m(
 // whole field rather than in one slab of it, which the strided rows of a
 // last-axis tile read at a higher HBM rate.
 struct TileRun {
-  int t0, t1;  // tile counts of the engine's launches stay below 2^31 (host-checked)
+  int t0, t1;  // the engine launches fewer than 2^31 - 2^16 tiles (host-checked)
   __device__ __forceinline__ explicit TileRun(long long ntiles)
       : t0((int)((long long)blockIdx.x * ntiles / gridDim.x)),
         t1((int)(((long long)blockIdx.x + 1) * ntiles / gridDim.x)) {}

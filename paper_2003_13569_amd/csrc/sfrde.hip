@@ -502,7 +502,8 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
   size_t lds = tile_bytes + std::max(ax.nfb * fold_bytes, res_bytes);
   lds = std::max<size_t>(lds, (size_t)threads * sizeof(double));
   if (lds > 160 * 1024) return SFRDE_OK;  // does not fit: FFT or dense kernels
-  if (g.ntiles > 0x7fffffffLL) return SFRDE_OK;  // the engine's tile indices are 32-bit
+  // the engine's tile indices are 32-bit, with room for one stride of the grid
+  if (g.ntiles > 0x7fff0000LL) return SFRDE_OK;
   p->lds_m[axis] = lds;
   // persistent grid: as many blocks as fit on the CUs at once
   const long long per_cu = 1;
