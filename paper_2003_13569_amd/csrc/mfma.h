@@ -216,13 +216,25 @@ struct MfmaXfF32 {
   }
   __device__ __forceinline__ bool two_buffers() const { return XAX && ax->nfb > 1; }
 
+  // Entries 64 and up of the fold buffer are stored rotated by four within
+  // each group of eight (item e of a work item at i0 >= 64 holds entry
+  // i0 + (e ^ 4)); the host orders the matrix fragments the same way, so the
+  // products are unchanged. The fold's LDS reads then never hit one bank
+  // twice: rows 64 apart share a bank at any tile pitch, and the two halves
+  // of a 16-lane row would otherwise read such rows at once.
   __device__ __forceinline__ void fold(const float* x) {
     if ((int)threadIdx.x >= FOLD_THREADS) return;
     float sv[8], dv[8];
+    const int rot = (threadIdx.x & 8) ? 4 : 0;  // i0 >= 64
     if (ffast) {
+      const float* xa0 = x + fa + rot * P;   // items 0..3: entries i0 + rot + e
+      const float* xa1 = x + fa - rot * P;   // items 4..7: entries i0 - rot + e
+      const float* xb0 = x + fbb - rot * P;  // their partners
+      const float* xb1 = x + fbb + rot * P;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float xa = x[fa + e * P], xb = x[fbb - e * P];
+        const float xa = e < 4 ? xa0[e * P] : xa1[e * P];
+        const float xb = e < 4 ? xb0[-e * P] : xb1[-e * P];
         sv[e] = xa + xb;
         dv[e] = xa - xb;
       }
@@ -230,7 +242,7 @@ struct MfmaXfF32 {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         int a, b;
-        fold_pair(*ax, i0 + e, a, b);
+        fold_pair(*ax, i0 + (e ^ rot), a, b);
         const float xa = a >= 0 ? x[a * P + col] : 0.f;
         const float xb = b >= 0 ? x[b * P + col] : 0.f;
         sv[e] = xa + xb;
@@ -242,7 +254,8 @@ struct MfmaXfF32 {
 
   // Fold from registers: v[0], v[1] hold entries i0 .. i0+7 of this thread's
   // line, v[2], v[3] entries n-8-i0 .. n-1-i0 (DCT-I / DST-I pairs i, n-1-i;
-  // items past the folded length are padding).
+  // items past the folded length are padding), each pair of float4 swapped
+  // where i0 >= 64 (the rotated order of fold()).
   __device__ __forceinline__ void fold_regs(const float4 (&v)[4]) {
     float sv[8], dv[8];
 #pragma unroll
@@ -1493,7 +1506,9 @@ __device__ __forceinline__ void combine_mode(const StageArgs<T>& a, T* buf, long
 // Inputs of the fold of an x tile (two species, 32 lines, n in {64, 128,
 // 256}, DCT-I / DST-I), read straight into registers: thread t takes line
 // (t/16) mod 32, entries i0 .. i0+7 and n-8-i0 .. n-1-i0 with i0 = 8 (t%16)
-// (padding items, i0 >= n/2, read entry 0 again and are dropped).
+// (padding items, i0 >= n/2, read entry 0 again and are dropped). Where
+// i0 >= 64 the two float4 of each group come in swapped order: the fold
+// buffer's rotated entries (MfmaXfF32::fold).
 struct XFoldLoads {
   float4 v[2][4];
   __device__ __forceinline__ void issue(const Geom& g, long long tile, const float* src) {
@@ -1501,14 +1516,15 @@ struct XFoldLoads {
     const int n = g.n;
     const int i0 = (threadIdx.x & 15) << 3;
     const int ic = 2 * i0 < n ? i0 : 0;
+    const int sw = (threadIdx.x & 8) ? 4 : 0;  // i0 >= 64
     const long long line = t * 32 + ((threadIdx.x >> 4) & 31);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const float* p = src + s * g.total + line * n;
-      v[s][0] = *reinterpret_cast<const float4*>(p + ic);
-      v[s][1] = *reinterpret_cast<const float4*>(p + ic + 4);
-      v[s][2] = *reinterpret_cast<const float4*>(p + n - 8 - ic);
-      v[s][3] = *reinterpret_cast<const float4*>(p + n - 4 - ic);
+      v[s][0] = *reinterpret_cast<const float4*>(p + ic + sw);
+      v[s][1] = *reinterpret_cast<const float4*>(p + ic + 4 - sw);
+      v[s][2] = *reinterpret_cast<const float4*>(p + n - 8 - ic + sw);
+      v[s][3] = *reinterpret_cast<const float4*>(p + n - 4 - ic - sw);
     }
   }
 };

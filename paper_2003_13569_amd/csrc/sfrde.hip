@@ -517,7 +517,10 @@ int setup_mfma_axis(sfrde_plan_s* p, int axis) {
       for (int ks = 0; ks < MF_KSMAX_F32; ++ks)
         for (int lane = 0; lane < 64; ++lane)
           for (int e = 0; e < 8; ++e) {
-            const double v = half_entry(t, rb, lane % 16, 32 * ks + 8 * (lane / 16) + e);
+            // folded entries 64 and up sit rotated by four within each group
+            // of eight in the engine's fold buffer: the same order here
+            const int k = 32 * ks + 8 * (lane / 16) + e;
+            const double v = half_entry(t, rb, lane % 16, k >= 64 ? k ^ 4 : k);
             const unsigned short h0 = host_f16(v);
             const unsigned short h1 = host_f16(v - host_f16_value(h0));
             frag[((((size_t)rb * MF_KSMAX_F32 + ks) * 2 + 0) * 64 + lane) * 8 + e] = h0;
