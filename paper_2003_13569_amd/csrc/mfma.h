@@ -734,13 +734,13 @@ struct XTileIO {
 // Adjoint reaction on an x tile in the XTileIO layout (every thread takes 4
 // consecutive points of a line, all species): the stored stage values are
 // read as vectors and the Neumann point weights formed from the coordinates.
-template <int NS>
+template <int NS, bool WP = true>
 __device__ __forceinline__ void xadj_reaction_vec(const StageArgs<float>& a, float* buf,
                                                   long long tile, double* pacc) {
   using IO = XTileIO<32>;
   const Geom& g = a.g;
   const TileRef tr = tile_ref(g, tile);
-  const bool want_p = a.rp_acc != nullptr;
+  const bool want_p = WP && a.rp_acc != nullptr;  // WP = false: never (host-checked)
   const int sh = IO::vshift(g);  // vectors per species 2^sh, a multiple of 512
   const int n = g.n;
   const int line0 = (int)(tile * 32);  // line index = y + n1 z (< 2^20)
@@ -1692,8 +1692,11 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
 }
 
 // NS > 0 (FAST FP32 launches of one or two species, chosen by the host): the
-// vector adjoint reaction of NS species only.
-template <typename T, class XF, bool FAST, int NS = 0>
+// vector adjoint reaction of NS species only. RF (two species, DCT-I /
+// DST-I, no reaction-parameter partials): the first transform folded
+// straight from registers, as in the forward x kernels (no LDS staging of
+// the input tile).
+template <typename T, class XF, bool FAST, int NS = 0, bool RF = false>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(StageArgs<T> a, MfmaAxisDev ax) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1703,6 +1706,30 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
   for (int k = 0; k < RXN_NP_MAX; ++k) pacc[k] = 0.0;
   const int S = a.g.spt;
   const int last = (int)(a.g.ntiles - 1);
+  if constexpr (RF && NS == 2 && FAST && std::is_same<T, float>::value && XF::XAX) {
+    XFoldLoads rl;
+    rl.issue(a.g, blockIdx.x, a.P);
+    for (int tile = blockIdx.x; tile < a.g.ntiles; tile += gridDim.x) {
+      const int next = tile + gridDim.x < last ? tile + gridDim.x : last;
+      xf.fold_regs(rl.v[0]);
+      __syncthreads();
+      xf.mfma_write(buf, !xf.two_buffers());
+      xf.use(1);
+      xf.fold_regs(rl.v[1]);
+      __syncthreads();
+      xf.mfma_write(buf + a.g.n * XF::P);
+      xf.use(0);
+      xadj_reaction_vec<NS, false>(a, buf, tile, pacc);
+      __syncthreads();
+      // next tile's input: in flight over the second transform and the store
+      // (issued earlier, its registers would be live across the reaction)
+      rl.issue(a.g, next, a.P);
+      xf(buf, S);
+      tile_store<T, XF::W, FAST, true>(a.g, tile, buf, a.P);
+      __syncthreads();
+    }
+    return;
+  }
   TilePipe<T, XF::W, FAST, true> pipe;
   pipe.issue(a.g, blockIdx.x, a.P);
   pipe.commit(a.g, blockIdx.x, a.P, buf);

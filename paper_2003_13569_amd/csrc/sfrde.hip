@@ -635,6 +635,7 @@ int set_lds_attrs(size_t bytes) {
                           reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, true, MODE_INIT, 1>),
                           reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, true, 1>),
                           reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, true, 2>),
+                          reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, true, 2, true>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, true>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true>),
                           reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, true, 1>),
@@ -1067,6 +1068,12 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
     if (std::is_same<T, float>::value && fast && p->S == 1)
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, true, 1>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
+    else if (std::is_same<T, float>::value && fast && p->S == 2 && p->mfax[0].direct &&
+             !p->rp_acc)
+      // DCT-I / DST-I, no reaction-parameter partials: the input folded
+      // straight from registers
+      hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, true, 2, true>), grid, block, p->lds_m[0], p->stream,
+                         a, p->mfax[0]);
     else if (std::is_same<T, float>::value && fast && p->S == 2)
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, true, 2>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
