@@ -97,10 +97,13 @@ def test_batch_adjoint_matches_oracle_per_member():
     p.close()
 
 
+@pytest.mark.parametrize("params", [True, False], ids=["params", "no-params"])
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-3)])
-def test_batch_adjoint_on_vector_paths_matches_oracle_per_member(dtype, tol):
+def test_batch_adjoint_on_vector_paths_matches_oracle_per_member(dtype, tol, params):
     """Ensemble adjoint on a grid whose axes take the vector paths (the
-    ensemble's z adjoint accumulates the kappa/alpha terms per point)."""
+    ensemble's z adjoint accumulates the kappa/alpha terms per point;
+    without reaction-parameter gradients the FP32 adjoint x kernel folds its
+    input from registers)."""
     wl = VEC_CASES[2]  # Gierer-Meinhardt 256 x 128, Neumann
     members = _members(wl, 2)
     u0 = np.stack([W.initial_fields(m) for m in members])
@@ -111,15 +114,18 @@ def test_batch_adjoint_on_vector_paths_matches_oracle_per_member(dtype, tol):
     ck = p.integrate(u, M, 0.0, K)
     g_u0 = torch.empty_like(u)
     gk, ga, gp = p.backward(ck, M, K, torch.tensor(wbar, dtype=TD[dtype], device="cuda"), 0.0,
-                            g_u0)
+                            g_u0, params=params)
     torch.cuda.synchronize()
+    assert (gp is None) == (not params)
     g_u0 = g_u0.double().cpu().numpy()
     S, npar = wl.nspecies, len(wl.params)
     for b, m in enumerate(members):
         ref = problem.gradients(m, u0[b], M, wbar[b])
         assert problem.rel_err(g_u0[b], ref["u0"]) <= (1e-10 if dtype == "f64" else 1e-4)
-        for key, got in (("kappa", gk[b * S:(b + 1) * S]), ("alpha", ga[b * S:(b + 1) * S]),
-                         ("params", gp[b * npar:(b + 1) * npar])):
+        checks = [("kappa", gk[b * S:(b + 1) * S]), ("alpha", ga[b * S:(b + 1) * S])]
+        if params:
+            checks.append(("params", gp[b * npar:(b + 1) * npar]))
+        for key, got in checks:
             r = ref[key]
             assert np.max(np.abs(np.array(got) - r)) <= tol * max(np.max(np.abs(r)), 1e-300), \
                 (b, key, got, r)
