@@ -844,6 +844,32 @@ __device__ __forceinline__ void pw_adj_reaction(const StageArgs<T>& a, T* buf, l
 // forward combine. G accumulates, per mode, y * g'(L) * x over every
 // coefficient application y_out = g(L) x of the forward step, for the kappa
 // and alpha gradients.
+// The adjoint's coefficient table values from L in FP64 (P13, Section 4's
+// rational forms; the C_R and C_Q slots hold the decrements 1 - R and 1 - Q,
+// as the tables do) and the derivatives in L of the coefficients themselves
+// (quotient rule, g' = (num' - g den') / den, D' = 18 + 12L + 3L^2,
+// Dh' = 72 + 24L + 3L^2).
+__device__ __forceinline__ void p13_table_derivs(double L, double tau, double* c, double* d) {
+  const double D = 24.0 + L * (18.0 + L * (6.0 + L));
+  const double Dh = 192.0 + L * (72.0 + L * (12.0 + L));
+  const double iD = 1.0 / D, iDh = 1.0 / Dh;
+  const double R = (24.0 - 6.0 * L) * iD, Q = (192.0 - 24.0 * L) * iDh;
+  const bool small = L < 1.0;
+  c[C_R] = small ? L * (24.0 + L * (6.0 + L)) * iD : 1.0 - R;
+  c[C_Q] = small ? L * (96.0 + L * (12.0 + L)) * iDh : 1.0 - Q;
+  c[C_PHI] = tau * (96.0 + L * (12.0 + L)) * iDh;
+  c[C_PHI1] = tau * (4.0 - L) * iD;
+  c[C_PHI2] = tau * (8.0 + 2.0 * L) * iD;
+  c[C_PHI3] = tau * (4.0 + L * (3.0 + L)) * iD;
+  const double dD = 18.0 + L * (12.0 + 3.0 * L), dDh = 72.0 + L * (24.0 + 3.0 * L);
+  d[C_R] = (-6.0 - R * dD) * iD;
+  d[C_Q] = (-24.0 - Q * dDh) * iDh;
+  d[C_PHI] = (tau * (12.0 + 2.0 * L) - c[C_PHI] * dDh) * iDh;
+  d[C_PHI1] = (-tau - c[C_PHI1] * dD) * iD;
+  d[C_PHI2] = (2.0 * tau - c[C_PHI2] * dD) * iD;
+  d[C_PHI3] = (tau * (3.0 + 2.0 * L) - c[C_PHI3] * dD) * iD;
+}
+
 template <typename T>
 __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, long long tile) {
   const Geom& g = a.g;
@@ -852,6 +878,9 @@ __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, lo
   const int ne = g.n * g.W;
   const long long tot = g.total;
   const long long cst = (long long)S * tot;
+  // FP64 P13 plans: the coefficients and their derivatives formed from L
+  // (one table read per point instead of up to eleven)
+  const bool from_l = std::is_same<T, double>::value && a.ltab != nullptr;
   for (int e = threadIdx.x; e < ne; e += blockDim.x) {
     int j, w;
     unpack(g, e, j, w);
@@ -863,56 +892,59 @@ __device__ __forceinline__ void pw_adj_combine(const StageArgs<T>& a, T* buf, lo
       const long long i = s * tot + idx;
       const T* cf = a.coef + i;
       const T* dc = a.dcoef ? a.dcoef + i : nullptr;
+      double cl[NCOEF], dl[NCOEF];
+      if (from_l) p13_table_derivs(double(a.ltab[i]), double(a.tau), cl, dl);
+      auto C = [&](int q) -> T { return from_l ? T(cl[q]) : cf[q * cst]; };
+      auto Dq = [&](int q) -> T { return from_l ? T(dl[q]) : dc[q * cst]; };
       T out;
       switch (a.mode) {
         case 0: {
           const T z = a.zh[i];
-          const T dQ = cf[C_Q * cst], cP = cf[C_PHI * cst];
-          a.aacc[i] = dec_mul(cf[C_R * cst], z);
+          const T dQ = C(C_Q), cP = C(C_PHI);
+          a.aacc[i] = dec_mul(C(C_R), z);
           a.ahat[i] = dec_mul(dQ, X);
-          a.gu[i] = cf[C_PHI1 * cst] * z - cP * X;
-          out = cf[C_PHI2 * cst] * z + T(2) * cP * X;
+          a.gu[i] = C(C_PHI1) * z - cP * X;
+          out = C(C_PHI2) * z + T(2) * cP * X;
           if (a.G) {
             const T uh = a.st_uhat[i];
             const T fu = a.st_fhat[0 * cst + i], fa = a.st_fhat[1 * cst + i];
             const T fb = a.st_fhat[2 * cst + i], fc = a.st_fhat[3 * cst + i];
             const T ah = dec_mul(dQ, uh) + cP * fu;
-            const T s1 = dc[C_R * cst] * uh + dc[C_PHI1 * cst] * fu +
-                         dc[C_PHI2 * cst] * (fa + fb) + dc[C_PHI3 * cst] * fc;
-            const T s2 = dc[C_Q * cst] * ah + dc[C_PHI * cst] * (T(2) * fb - fu);
+            const T s1 = Dq(C_R) * uh + Dq(C_PHI1) * fu + Dq(C_PHI2) * (fa + fb) + Dq(C_PHI3) * fc;
+            const T s2 = Dq(C_Q) * ah + Dq(C_PHI) * (T(2) * fb - fu);
             a.G[i] += double(z) * double(s1) + double(X) * double(s2);
           }
           break;
         }
         case 1: {
           const T z = a.zh[i];
-          a.aacc[i] += dec_mul(cf[C_Q * cst], X);
-          out = cf[C_PHI2 * cst] * z + cf[C_PHI * cst] * X;
+          a.aacc[i] += dec_mul(C(C_Q), X);
+          out = C(C_PHI2) * z + C(C_PHI) * X;
           if (a.G) {
             const T uh = a.st_uhat[i], fa = a.st_fhat[1 * cst + i];
-            a.G[i] += double(X) * double(dc[C_Q * cst] * uh + dc[C_PHI * cst] * fa);
+            a.G[i] += double(X) * double(Dq(C_Q) * uh + Dq(C_PHI) * fa);
           }
           break;
         }
         case 2: {
           const T A = a.ahat[i] + X;
-          a.aacc[i] += dec_mul(cf[C_Q * cst], A);
-          out = a.gu[i] + cf[C_PHI * cst] * A;
+          a.aacc[i] += dec_mul(C(C_Q), A);
+          out = a.gu[i] + C(C_PHI) * A;
           if (a.G) {
             const T uh = a.st_uhat[i], fu = a.st_fhat[0 * cst + i];
-            a.G[i] += double(A) * double(dc[C_Q * cst] * uh + dc[C_PHI * cst] * fu);
+            a.G[i] += double(A) * double(Dq(C_Q) * uh + Dq(C_PHI) * fu);
           }
           break;
         }
         case 3: {
           const T zn = a.aacc[i] + X;
           a.zh[i] = zn;
-          out = a.last ? zn : cf[C_PHI3 * cst] * zn;
+          out = a.last ? zn : C(C_PHI3) * zn;
           break;
         }
         default:  // MODE_INIT: X is the transformed cotangent of u(T)
           a.zh[i] = X;
-          out = cf[C_PHI3 * cst] * X;
+          out = C(C_PHI3) * X;
           break;
       }
       cell = a.cs * out;

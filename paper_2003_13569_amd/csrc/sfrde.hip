@@ -1247,8 +1247,11 @@ int carve_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_theta
     take((void**)&p->thp, (size_t)4 * p->grid_m[p->ndim - 1] * sizeof(double));
   } else if (want_theta) {
     take((void**)&p->G, field_elems(p) * sizeof(double));
-    take(&p->dcoef, NCOEF * f);
-    fill_dcoef = true;
+    // FP64 P13 plans form the coefficient derivatives from L in the combine
+    if (!(p->ltab && p->dtype == SFRDE_F64)) {
+      take(&p->dcoef, NCOEF * f);
+      fill_dcoef = true;
+    }
   }
   if (want_p) take((void**)&p->rp_acc, (size_t)p->B * MAX_PARAMS * rp_blocks(p) * sizeof(double));
   const long long need = RED_OUT + (long long)p->B * RED_PER_MEMBER;
@@ -1285,7 +1288,8 @@ int ensure_backward_buffers(sfrde_plan_s* p, long long seg_steps, bool want_thet
     TRY(dev_alloc(p, (void**)&p->thp, (size_t)4 * p->grid_m[p->ndim - 1] * sizeof(double)));
   } else if (want_theta) {
     TRY(dev_alloc(p, (void**)&p->G, field_elems(p) * sizeof(double)));
-    if (!p->dcoef) {
+    // FP64 P13 plans form the coefficient derivatives from L in the combine
+    if (!p->dcoef && !(p->ltab && p->dtype == SFRDE_F64)) {
       TRY(dev_alloc(p, &p->dcoef, NCOEF * f));
       TRY(coef_tables(p, 1, p->dcoef));
     }
