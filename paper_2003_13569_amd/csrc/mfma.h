@@ -1695,8 +1695,10 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_zstage_m(
 // vector adjoint reaction of NS species only. RF (two species, DCT-I /
 // DST-I, no reaction-parameter partials): the first transform folded
 // straight from registers, as in the forward x kernels (no LDS staging of
-// the input tile).
-template <typename T, class XF, bool FAST, int NS = 0, bool RF = false>
+// the input tile). KIND >= 0 (FP64, two species, chosen by the host): only
+// the adjoint reaction of that kind is compiled (the kernel holding every
+// species count and kind is past the size of the instruction cache).
+template <typename T, class XF, bool FAST, int NS = 0, bool RF = false, int KIND = -1>
 __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(StageArgs<T> a, MfmaAxisDev ax) {
   to_member(a);
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1741,6 +1743,8 @@ __global__ __launch_bounds__(XF::THREADS, XF::MIN_WAVES_PER_EU) void k_xadj_m(St
       xadj_reaction_vec<NS>(a, buf, tile, pacc);
     else if constexpr (FAST && std::is_same<T, float>::value && XF::XAX)
       xadj_reaction_fast(a, buf, tile, pacc);
+    else if constexpr (KIND >= 0)
+      pw_adj_reaction_n<T, 2, KIND>(a, buf, tile, pacc);
     else
       pw_adj_reaction(a, buf, tile, pacc);
     __syncthreads();

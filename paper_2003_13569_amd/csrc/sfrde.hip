@@ -614,6 +614,15 @@ int set_lds_attrs(size_t bytes) {
       reinterpret_cast<const void*>(&k_zadj_m<T, XfZ<T>, false>),
       reinterpret_cast<const void*>(&k_single_m<T, XfX<T>, false>),
       reinterpret_cast<const void*>(&k_single_m<T, XfZ<T>, false>)};
+  if constexpr (std::is_same<T, double>::value) {
+    const void* kinds[] = {
+        reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, false, 2, false, RXN_LINEAR>),
+        reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, false, 2, false, RXN_FHN>),
+        reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, false, 2, false, RXN_GRAY_SCOTT>),
+        reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, false, 2, false, RXN_SCHNAKENBERG>),
+        reinterpret_cast<const void*>(&k_xadj_m<T, XfX<T>, false, 2, false, RXN_GM>)};
+    for (const void* f : kinds) fns.push_back(f);
+  }
   if constexpr (std::is_same<T, float>::value) {
     const void* fast[] = {reinterpret_cast<const void*>(&k_xstage_m<T, XfX<T>, true>),
                           reinterpret_cast<const void*>(&k_zstage_m<T, XfZ<T>, -1, true>),
@@ -1055,6 +1064,14 @@ int resume_t(sfrde_plan_s* p, const void* ckpt, long long slot, void* state, lon
 }
 
 // --------------------------------------------------------------------------
+// The FP64 adjoint x kernel of reaction kind KIND (two species).
+template <int KIND>
+void launch_xadj64(sfrde_plan_s* p, dim3 grid, dim3 block, size_t lds,
+                   const StageArgs<double>& a) {
+  hipLaunchKernelGGL((k_xadj_m<double, XfX<double>, false, 2, false, KIND>), grid, block, lds,
+                     p->stream, a, p->mfax[0]);
+}
+
 template <typename T>
 int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
   StageArgs<T> a = stage_args<T>(p, 0, p->Pa);
@@ -1065,6 +1082,20 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
   if (p->use_m[0]) {
     const dim3 grid(p->grid_m[0], p->B), block(XfX<T>::THREADS);
     const bool fast = use_fast<T>(p, 0, {p->Pa});
+    if constexpr (std::is_same<T, double>::value) {
+      // FP64, two species: the instance of the plan's reaction kind
+      if (p->S == 2 && p->rxn.kind <= RXN_GM) {
+        const size_t lds = p->lds_m[0];
+        switch (p->rxn.kind) {
+          case RXN_LINEAR: launch_xadj64<RXN_LINEAR>(p, grid, block, lds, a); break;
+          case RXN_FHN: launch_xadj64<RXN_FHN>(p, grid, block, lds, a); break;
+          case RXN_GRAY_SCOTT: launch_xadj64<RXN_GRAY_SCOTT>(p, grid, block, lds, a); break;
+          case RXN_SCHNAKENBERG: launch_xadj64<RXN_SCHNAKENBERG>(p, grid, block, lds, a); break;
+          default: launch_xadj64<RXN_GM>(p, grid, block, lds, a); break;
+        }
+        goto xadj_launched;
+      }
+    }
     if (std::is_same<T, float>::value && fast && p->S == 1)
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, true, 1>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
@@ -1083,6 +1114,7 @@ int launch_xadj(sfrde_plan_s* p, int stage, const StepStore<T>& st) {
     else
       hipLaunchKernelGGL((k_xadj_m<T, XfX<T>, false>), grid, block, p->lds_m[0], p->stream, a,
                          p->mfax[0]);
+  xadj_launched:;
   } else if (p->use_f[0]) {
     hipLaunchKernelGGL((k_xadj<T, FftXf, true>), dim3((unsigned)a.g.ntiles, p->B), dim3(p->thr_f[0]),
                        p->lds_f[0], p->stream, a);
