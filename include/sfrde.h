@@ -62,7 +62,7 @@ enum sfrde_status {
   SFRDE_ENOMEM = -2,       /* device or host allocation failed */
   SFRDE_EDEVICE = -3,      /* a HIP runtime call failed */
   SFRDE_ENONFINITE = -4,   /* a stage value or reaction became NaN/Inf */
-  SFRDE_EUNSUPPORTED = -5, /* valid request this build does not support */
+  SFRDE_EUNSUPPORTED = -5, /* valid request the library does not support */
   SFRDE_ESTATE = -6        /* checkpoint incompatible with the request */
 };
 
